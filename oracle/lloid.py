@@ -1,0 +1,359 @@
+"""Plain FP64 CPU oracle of the LLOID multirate matched filter.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports this module;
+only the tests, the smoke check and the CPU-baseline leg of the benchmark do.
+It shares no code with the GPU library.  Every step follows the paper
+(Sec. II.C, "The LLOID filtering algorithm") in its own order and notation,
+in float64, with NumPy matmuls and strided window views as the only library
+primitives:
+
+  downsample  d^s  -- Eq. (sinc) kernel, Sec. II.C.2 "Downsampling"
+  correlate   y^s_l -- basis cross-correlation, Sec. II.C.2 "Filtering and
+                       reconstruction", shifted per the pre-synchronisation
+                       equation of Sec. II.C.3
+  reconstruct y'^s_i -- mixing with sigma^s_l nu^s_il (same paragraph)
+  upsample-and-add  -- Eq. (upsample) polyphase form, Sec. II.C.2
+                       "Upsampling SNR segments" / "Combining SNR segments",
+                       recursion of the pre-synchronisation equation
+  triggers          -- Sec. II.D.1: max |complex SNR| per template per window
+
+Readings of points the paper leaves open are stated where they are used:
+
+* R1 downsampler gain: Eq. (sinc) fixes g[c]=1 but no normalisation.  We use
+  g_hat = sqrt(D) g / sum(g): unit DC gain times sqrt(D), which pairs with
+  slice templates sampled at f^s and scaled by sqrt(D), so a band-limited
+  slice gives the same correlation as at the top rate.
+* R2 the downsampler goes from the top rate straight to f^s with one kernel
+  of factor D = F/f^s (not a cascade of halvings).
+* R3 one upsampling stage per pair of consecutive distinct slice rates,
+  factor p = their ratio (the top rate is always the last level).
+* R4 Eq. (upsample)'s special case y[i] = x[i/f] holds for the zero-phase
+  indexing y[i] = sum_k x[floor(i/f) + N_up - k] z_{i mod f}[k]; the causal
+  sum as printed delays by N_up input samples.  We take the zero-phase form;
+  the N_up look-ahead it needs is exactly what pre-synchronisation absorbs.
+* R5 polyphase taps k f + j beyond the kernel's last index 2c are zero.
+* R6 N_up counts input (lower-rate) samples: 2 f N_up + 1 taps at the
+  output rate, 2 N_up + 1 taps per phase.
+* R7 delays in the pre-synchronisation equation are converted to samples at
+  f^s; the integer look-ahead of each level follows from the index ranges.
+* R8 the correlation output index is the coalescence time: the latest tap
+  (n = N^s - 1) meets data t^s before it, so a signal merging at t peaks at t.
+* R9 rows 2i / 2i+1 are the cosine (real) and sine (imaginary) filters of
+  template i; z_i = rho_2i + i rho_2i+1.
+* R10 discrete SNR is sum h d with unit-norm real filters and unit-variance
+  strain, so E|z|^2 = 2 in noise (the xi^2 denominator 2 - 2|R|^2 of
+  Sec. II.D.2 has the same normalisation).
+* R13 the trigger window is the stride; the max is reported for every
+  template, with a separate flag for |z| >= 4.
+* R14 argmax ties resolve to the lowest index.
+* R15 history before the first sample and gap strides are zeros.
+* normalisation: each real row is scaled so that sum_s sum_l W^s[r,l]^2 = 1
+  (the reconstructed template has unit norm), computed in float64.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+from numpy.lib.stride_tricks import sliding_window_view
+
+N_DOWN = 32       # downsampler half-length at the target rate (Sec. II.C.2)
+N_UP = 8          # upsampler half-length in input samples (Sec. II.C.2)
+SNR_THRESHOLD = 4.0   # trigger threshold (Sec. II.D.1)
+
+
+@dataclass
+class OracleConfig:
+    sample_rate: int
+    n_down: int = N_DOWN
+    n_up: int = N_UP
+    normalize: bool = True
+    snr_threshold: float = SNR_THRESHOLD
+
+
+# ---------------------------------------------------------------------------
+# Resampling kernels (Eq. (sinc), Sec. II.C.2)
+# ---------------------------------------------------------------------------
+
+def sinc_windowed_sinc(f: int, c: int) -> np.ndarray:
+    """g[k] = sinc((k-c)/f) * sinc((k-c)/c), k = 0..2c, g[c] = 1 (Eq. (sinc)).
+
+    numpy's sinc(x) = sin(pi x)/(pi x) with sinc(0) = 1, which is the form of
+    both factors of the equation."""
+    u = np.arange(2 * c + 1, dtype=np.float64) - c
+    return np.sinc(u / f) * np.sinc(u / c)
+
+
+def downsample_kernel(D: int, n_down: int = N_DOWN) -> Tuple[np.ndarray, int]:
+    """Normalised decimation kernel g_hat = sqrt(D) g / sum g, c = D N_down
+    (reading R1)."""
+    c = D * n_down
+    g = sinc_windowed_sinc(D, c)
+    return np.sqrt(D) * g / g.sum(), c
+
+
+def upsample_kernel(p: int, n_up: int = N_UP) -> Tuple[np.ndarray, int]:
+    """Interpolation kernel: Eq. (sinc) with factor p and c = p N_up,
+    unnormalised (g[c] = 1), 2 p N_up + 1 taps (reading R6)."""
+    c = p * n_up
+    return sinc_windowed_sinc(p, c), c
+
+
+def polyphase_subkernels(p: int, n_up: int = N_UP) -> np.ndarray:
+    """z_j[k] = g[k p + j], j < p, k = 0..2 N_up; zero past 2c (reading R5)."""
+    g, c = upsample_kernel(p, n_up)
+    z = np.zeros((p, 2 * n_up + 1))
+    for j in range(p):
+        for k in range(2 * n_up + 1):
+            if k * p + j <= 2 * c:
+                z[j, k] = g[k * p + j]
+    return z
+
+
+# ---------------------------------------------------------------------------
+# Index helpers
+# ---------------------------------------------------------------------------
+
+def take(x: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    """x[..., lo:hi] with zeros outside x's support (reading R15)."""
+    n = x.shape[-1]
+    out = np.zeros(x.shape[:-1] + (hi - lo,), dtype=np.float64)
+    a, b = max(lo, 0), min(hi, n)
+    if b > a:
+        out[..., a - lo:b - lo] = x[..., a:b]
+    return out
+
+
+def rate_chain(bank, top_rate: int) -> List[int]:
+    """Distinct slice rates in decreasing order, starting at the top rate
+    (reading R3)."""
+    rates = sorted({int(s.rate) for s in bank.slices} | {int(top_rate)}, reverse=True)
+    for r in rates:
+        if top_rate % r or (top_rate // r) & (top_rate // r - 1):
+            raise ValueError(f"rate {r} is not the top rate over a power of two")
+    return rates
+
+
+def level_ranges(chain: Sequence[int], t_lo: int, t_hi: int, n_up: int = N_UP) -> List[Tuple[int, int]]:
+    """Index range [lo_j, hi_j) of each level's stream needed for top-rate
+    outputs [t_lo, t_hi): the zero-phase polyphase sum at level j-1 reads
+    level j from floor(i/p) - N_up to floor(i/p) + N_up."""
+    out = [(t_lo, t_hi)]
+    for j in range(1, len(chain)):
+        p = chain[j - 1] // chain[j]
+        lo, hi = out[-1]
+        out.append((lo // p - n_up, (hi - 1) // p + n_up + 1))
+    return out
+
+
+def lookahead(chain: Sequence[int], n_up: int = N_UP) -> List[int]:
+    """Samples at level j beyond the end of the current stride that level j
+    must supply: the cumulative upsampling half-lengths of the
+    pre-synchronisation equation (Sec. II.C.3) in level-j samples."""
+    F = chain[0]
+    rng = level_ranges(chain, 0, F, n_up)
+    return [hi - r for (lo, hi), r in zip(rng, chain)]
+
+
+def latency_violations(bank, top_rate: int, n_down: int = N_DOWN, n_up: int = N_UP) -> List[int]:
+    """Slices whose delay is shorter than the downsampling plus cumulative
+    upsampling look-ahead (Sec. II.C.2 "Combining SNR segments": no extra
+    latency as long as the delays exceed the filter lengths).  Such a slice
+    would need strain from the future of the current stride."""
+    chain = rate_chain(bank, top_rate)
+    la = lookahead(chain, n_up)
+    bad = []
+    for i, s in enumerate(bank.slices):
+        j = chain.index(int(s.rate))
+        need = la[j] + (n_down if s.rate != top_rate else 0)
+        if s.delay < need:
+            bad.append(i)
+    return bad
+
+
+# ---------------------------------------------------------------------------
+# The steps
+# ---------------------------------------------------------------------------
+
+def normalized_mixing(bank) -> List[np.ndarray]:
+    """W~^s = W^s / n_r, n_r^2 = sum_s sum_l W^s[r,l]^2 in float64."""
+    n2 = sum((np.asarray(s.mixing, np.float64) ** 2).sum(axis=1) for s in bank.slices)
+    n = np.sqrt(n2)
+    n[n == 0] = 1.0
+    return [np.asarray(s.mixing, np.float64) / n[:, None] for s in bank.slices]
+
+
+def downsample(x: np.ndarray, D: int, m_lo: int, m_hi: int, n_down: int = N_DOWN) -> np.ndarray:
+    """d_D[m] = sum_{k=0}^{2c} g_hat[k] x[D m + k - c], m in [m_lo, m_hi)
+    (Eq. (sinc) kernel, zero-phase; readings R1, R2)."""
+    if D == 1:
+        return take(x, m_lo, m_hi)
+    g, c = downsample_kernel(D, n_down)
+    seg = take(x, D * m_lo - c, D * (m_hi - 1) + c + 1)
+    win = sliding_window_view(seg, 2 * c + 1)[::D]      # win[i, k] = x[D(m_lo+i) - c + k]
+    return win @ g
+
+
+def correlate(U: np.ndarray, d: np.ndarray, d_lo: int, delay: int, q_lo: int, q_hi: int) -> np.ndarray:
+    """y_l[q] = sum_{n<N} u_l[n] d[q - delay - (N-1) + n], q in [q_lo, q_hi).
+
+    The basis correlation of Sec. II.C.2 with the slice delay of the
+    pre-synchronisation equation; index q is the coalescence time (R8).
+    ``d`` holds the downsampled stream starting at index d_lo."""
+    L, N = U.shape
+    a = q_lo - delay - (N - 1) - d_lo
+    seg = d[a:a + (q_hi - q_lo) + N - 1]
+    assert a >= 0 and seg.shape[0] == (q_hi - q_lo) + N - 1
+    H = sliding_window_view(seg, N)                     # H[i, n] = d[q_lo + i - delay - N + 1 + n]
+    return U @ H.T
+
+
+def upsample(a: np.ndarray, a_lo: int, p: int, i_lo: int, i_hi: int, n_up: int = N_UP) -> np.ndarray:
+    """(H_up a)[i] = sum_{k=0}^{2 N_up} a[floor(i/p) + N_up - k] z_{i mod p}[k]
+    for i in [i_lo, i_hi) (Eq. (upsample), zero-phase reading R4).
+    ``a`` is [rows, n] holding indices a_lo .. a_lo + n - 1."""
+    z = polyphase_subkernels(p, n_up)
+    i = np.arange(i_lo, i_hi)
+    q, ph = i // p, i % p
+    out = np.zeros((a.shape[0], i_hi - i_lo))
+    for k in range(2 * n_up + 1):
+        src = q + n_up - k - a_lo
+        assert src.min() >= 0 and src.max() < a.shape[1]
+        out += a[:, src] * z[ph, k][None, :]
+    # the equation's first case: phase-0 outputs are the input samples
+    zero = ph == 0
+    out[:, zero] = a[:, q[zero] - a_lo]
+    return out
+
+
+def snr_series(x: np.ndarray, bank, cfg: OracleConfig, t_lo: int, t_hi: int,
+               mixing: Optional[List[np.ndarray]] = None) -> np.ndarray:
+    """Real SNR streams rho[r, t] for top-rate times t in [t_lo, t_hi).
+
+    x is one detector's whitened strain at the top rate (zero outside its
+    support).  Lowest rate first: A_J = sum of z^s at R_J; then
+    A_j = H_up(A_{j+1}) + sum_{f^s = R_j} z^s, z^s = W~^s y^s, up to the top
+    rate (recursion of the pre-synchronisation equation, Sec. II.C.3)."""
+    F = cfg.sample_rate
+    chain = rate_chain(bank, F)
+    ranges = level_ranges(chain, t_lo, t_hi, cfg.n_up)
+    if mixing is None:
+        mixing = normalized_mixing(bank) if cfg.normalize else [np.asarray(s.mixing, np.float64) for s in bank.slices]
+    rows = 2 * bank.n_templates
+    # one downsampled stream per distinct rate, over the union of needed indices
+    need: Dict[int, Tuple[int, int]] = {}
+    for s in bank.slices:
+        j = chain.index(int(s.rate))
+        lo, hi = ranges[j]
+        a, b = lo - s.delay - (s.n_taps - 1), hi - s.delay
+        if s.rate in need:
+            a, b = min(a, need[s.rate][0]), max(b, need[s.rate][1])
+        need[s.rate] = (a, b)
+    streams = {r: (a, downsample(x, F // r, a, b, cfg.n_down)) for r, (a, b) in need.items()}
+    A = None
+    for j in range(len(chain) - 1, -1, -1):
+        lo, hi = ranges[j]
+        acc = np.zeros((rows, hi - lo))
+        if A is not None:
+            acc += upsample(A, ranges[j + 1][0], chain[j] // chain[j + 1], lo, hi, cfg.n_up)
+        for s, W in zip(bank.slices, mixing):
+            if s.rate != chain[j]:
+                continue
+            d_lo, d = streams[s.rate]
+            y = correlate(np.asarray(s.basis, np.float64), d, d_lo, s.delay, lo, hi)
+            acc += W @ y
+        A = acc
+    return A
+
+
+def complex_snr(rho: np.ndarray) -> np.ndarray:
+    """z_i = rho_{2i} + i rho_{2i+1} (reading R9)."""
+    return rho[0::2] + 1j * rho[1::2]
+
+
+@dataclass
+class Peaks:
+    snr: np.ndarray      # max |z| per template
+    index: np.ndarray    # lowest index attaining it, within the window
+    value: np.ndarray    # complex z at that index
+    above: np.ndarray    # snr >= threshold
+
+
+def window_peaks(z: np.ndarray, threshold: float = SNR_THRESHOLD) -> Peaks:
+    """Trigger per template over one window (Sec. II.D.1): maximum modulus of
+    the complex SNR, its first index, the value there, and the >= rho flag."""
+    p2 = z.real ** 2 + z.imag ** 2
+    idx = np.argmax(p2, axis=1)
+    val = z[np.arange(z.shape[0]), idx]
+    snr = np.abs(val)
+    return Peaks(snr, idx, val, snr >= threshold)
+
+
+def lloid_filter(x: np.ndarray, bank, cfg: OracleConfig, n_strides: Optional[int] = None,
+                 first_stride: int = 0) -> Tuple[np.ndarray, List[Peaks]]:
+    """Batch form: complex SNR for strides [first, first + n) of 1 s each and
+    their per-stride triggers.  x is [n_samples] (one detector)."""
+    F = cfg.sample_rate
+    if n_strides is None:
+        n_strides = x.shape[-1] // F - first_stride
+    zs, pk = [], []
+    for k in range(first_stride, first_stride + n_strides):
+        z = complex_snr(snr_series(x, bank, cfg, k * F, (k + 1) * F))
+        zs.append(z)
+        pk.append(window_peaks(z, cfg.snr_threshold))
+    return np.concatenate(zs, axis=1) if zs else np.zeros((bank.n_templates, 0), complex), pk
+
+
+class LloidStream:
+    """Streaming form: push strides in order; each push returns the complex
+    SNR for the pushed interval, computed from the strain received so far only
+    (the future is unknown and taken as zero).  Equals the batch form exactly
+    when no slice violates the latency condition."""
+
+    def __init__(self, bank, cfg: OracleConfig, n_samples_hint: int = 0):
+        self.bank, self.cfg = bank, cfg
+        self.x = np.zeros(0)
+        self.mixing = normalized_mixing(bank) if cfg.normalize else None
+
+    def push(self, chunk: np.ndarray, gap: bool = False) -> np.ndarray:
+        chunk = np.zeros(len(chunk)) if gap else np.asarray(chunk, np.float64)
+        t0 = self.x.shape[0]
+        self.x = np.concatenate([self.x, chunk])
+        rho = snr_series(self.x, self.bank, self.cfg, t0, self.x.shape[0], self.mixing)
+        return complex_snr(rho)
+
+    def state(self) -> np.ndarray:
+        return self.x.copy()
+
+    def load(self, state: np.ndarray) -> None:
+        self.x = state.copy()
+
+
+# ---------------------------------------------------------------------------
+# Direct matched filter (Eq. of Sec. II.C, discrete form) for pins
+# ---------------------------------------------------------------------------
+
+def brute_force(x: np.ndarray, templates: np.ndarray, t_lo: int, t_hi: int) -> np.ndarray:
+    """rho_r[t] = sum_j h_r(tau_j) x[t - j] at the top rate, tau_j = j/F
+    (the time-domain matched filter with whitened data and templates,
+    discrete, readings R8 and R10).  templates: [2M, n]."""
+    n = templates.shape[1]
+    seg = take(x, t_lo - n + 1, t_hi)
+    H = sliding_window_view(seg, n)          # H[i, m] = x[t_lo + i - n + 1 + m]
+    return templates[:, ::-1] @ H.T          # m = n-1-j
+
+
+def concatenated_filters(bank, top_rate: int, mixing: Optional[List[np.ndarray]] = None) -> np.ndarray:
+    """For a bank whose slices are all at the top rate: the full-rate filters
+    h_r(tau_j) obtained by placing W~^s U^s at delays t^s (reversed to
+    tau order).  Used to pin correlation + mixing + slicing + delays."""
+    if mixing is None:
+        mixing = [np.asarray(s.mixing, np.float64) for s in bank.slices]
+    n = max(s.delay + s.n_taps for s in bank.slices)
+    out = np.zeros((2 * bank.n_templates, n))
+    for s, W in zip(bank.slices, mixing):
+        assert s.rate == top_rate
+        R = W @ np.asarray(s.basis, np.float64)        # [2M, N], chronological taps
+        out[:, s.delay:s.delay + s.n_taps] += R[:, ::-1]   # tau index j = delay + N-1-m
+    return out
