@@ -1,0 +1,208 @@
+/*
+ * lloid.h -- C ABI of the MI355X LLOID filtering core.
+ *
+ * LLOID (Low-Latency Online Inspiral Detection) filters whitened strain with
+ * a template bank compressed by time slicing and SVD (Sec. II.C of the SGNL
+ * paper, arXiv:2511.04730).  Per 1-s stride and detector the library
+ *   1. decimates the strain to every slice rate with the sinc-windowed-sinc
+ *      kernel of Eq. (sinc)                                  (Sec. II.C.2),
+ *   2. correlates each slice's orthonormal basis filters u^s_l with the
+ *      stream at its rate, reading it at the pre-synchronised offset of the
+ *      recursion equation of Sec. II.C.3,
+ *   3. reconstructs every template's SNR at that rate with the mixing
+ *      matrix sigma^s_l nu^s_il                              (Sec. II.C.2),
+ *   4. upsamples with the polyphase form of Eq. (upsample) and adds, lowest
+ *      rate first, up to the top rate                        (Sec. II.C.2-3),
+ *   5. reports per template the maximum |complex SNR| in the stride, its
+ *      index, its value and whether it reaches the threshold (Sec. II.D.1).
+ * The SNR for stride k covers top-rate samples [kF, (k+1)F): no latency is
+ * added, as long as every slice's delay covers the resampling look-ahead
+ * (Sec. II.C.2 "Combining SNR segments").
+ *
+ * Conventions
+ *   - Signatures use only C types; device buffers are plain pointers to
+ *     device memory; streams are hipStream_t passed as void*.
+ *   - Every call returns an lloid_status.  Argument and shape errors are
+ *     detected on the host before anything is enqueued.  A HIP launch or
+ *     copy error is returned as LLOID_E_HIP; an asynchronous device error is
+ *     reported by the next call that synchronises.
+ *   - No call throws or aborts.  A plan must not be used by two host
+ *     threads at once; distinct plans are independent.
+ *   - Rows 2i and 2i+1 of a mixing matrix are the cosine (real) and sine
+ *     (imaginary) filters of template i; complex SNR z_i = rho_2i + i rho_2i+1.
+ */
+#ifndef LLOID_H
+#define LLOID_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LLOID_OK = 0,
+    LLOID_E_ARG = -1,         /* NULL pointer, out-of-range enum or count       */
+    LLOID_E_SHAPE = -2,       /* inconsistent sizes (rates, taps, basis counts) */
+    LLOID_E_LATENCY = -3,     /* a slice delay shorter than its look-ahead      */
+    LLOID_E_NOMEM = -4,       /* device or host allocation failed               */
+    LLOID_E_HIP = -5,         /* a HIP runtime call failed                      */
+    LLOID_E_STATE = -6,       /* call not valid in the plan's current state     */
+    LLOID_E_UNSUPPORTED = -7  /* valid request this build does not implement   */
+} lloid_status;
+
+/* Arithmetic of the correlation and mixing contractions (accumulation is
+ * always FP32).  FP32: FP32 operands.  BF16X3: both operands of both
+ * contractions split into bf16 hi + lo parts, three products (hi*hi + hi*lo +
+ * lo*hi).  FP16: fp16 basis and mixing, strain and basis outputs split into
+ * fp16 hi + lo.  FP8_BF16: fp8 e4m3 correlation with a power-of-two scale
+ * per basis vector and per stride, bf16x3 mixing. */
+typedef enum {
+    LLOID_FP32 = 0,
+    LLOID_BF16X3 = 1,
+    LLOID_FP16 = 2,
+    LLOID_FP8_BF16 = 3
+} lloid_precision;
+
+/* One time slice of one bank (Sec. II.C.1).
+ *   rate_hz  f^s, the top rate divided by a power of two (1 allowed)
+ *   delay    t^s * f^s: time before merger of the slice's latest tap, in
+ *            samples at f^s
+ *   n_taps   N^s; n_basis L^s with 1 <= L^s <= 160 (and at most 160 basis
+ *            vectors per bank and rate, each count rounded up to 16)
+ *   basis    host, row-major [L^s][N^s], float64: u^s_l[n], taps in
+ *            chronological order (column N^s-1 is closest to merger)
+ *   mixing   host, row-major [2M][L^s], float64: sigma^s_l nu^s_il        */
+typedef struct {
+    int32_t rate_hz;
+    int64_t delay;
+    int32_t n_taps;
+    int32_t n_basis;
+    const double *basis;
+    const double *mixing;
+} lloid_slice;
+
+typedef struct {
+    int32_t n_templates;       /* M complex templates (2M real filters) */
+    int32_t n_slices;
+    const lloid_slice *slices;
+} lloid_bank;
+
+typedef struct {
+    int32_t sample_rate_hz;    /* F, the top rate; one stride = F samples        */
+    int32_t n_detectors;       /* 1..32                                          */
+    int32_t n_down;            /* decimator half-length at the target rate (32)  */
+    int32_t n_up;              /* interpolator half-length, input samples (8)    */
+    int32_t precision;         /* lloid_precision                                */
+    int32_t normalize;         /* 1: scale each real row to unit reconstructed
+                                  norm sum_s sum_l W^s[r,l]^2 = 1, in FP64       */
+    float snr_threshold;       /* trigger threshold on |z| (4.0)                 */
+} lloid_config;
+
+/* Trigger of one template in one stride (Sec. II.D.1): the maximum |z| over
+ * the stride, the lowest in-stride index attaining it, z there, and
+ * above = (snr >= threshold). 20 bytes. */
+typedef struct {
+    float snr;
+    int32_t index;
+    float re;
+    float im;
+    int32_t above;
+} lloid_peak;
+
+typedef struct lloid_plan lloid_plan;
+
+/* Build a plan: validates every bank, groups slices by rate, derives the
+ * pre-synchronised read offsets, copies the banks to the device (the caller
+ * may free its arrays on return), normalises the mixing rows in FP64 on the
+ * device and converts them to the chosen precision, and allocates the
+ * per-detector history buffers.  The plan starts at stride 0 with zero
+ * history.  `stream` (hipStream_t or NULL) orders the set-up work; the call
+ * synchronises it before returning.
+ * Errors: LLOID_E_ARG, LLOID_E_SHAPE, LLOID_E_LATENCY (a slice needs strain
+ * from the future of the stride), LLOID_E_NOMEM, LLOID_E_HIP. */
+lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *banks,
+                               int32_t n_banks, void *stream, lloid_plan **out);
+
+void lloid_plan_destroy(lloid_plan *plan);
+
+/* Sizes and offsets of a plan's outputs (see lloid_push_stride). */
+typedef enum {
+    LLOID_Q_N_BANKS = 0,
+    LLOID_Q_TOTAL_TEMPLATES = 1,     /* sum of M_b                                */
+    LLOID_Q_SERIES_FLOATS = 2,       /* floats of one stride's SNR output         */
+    LLOID_Q_N_PEAKS = 3,             /* lloid_peak entries per stride             */
+    LLOID_Q_BANK_SERIES_OFFSET = 4,  /* index = bank: float offset of its block   */
+    LLOID_Q_BANK_PEAK_OFFSET = 5,    /* index = bank: entry offset of its block   */
+    LLOID_Q_BANK_TEMPLATES = 6,      /* index = bank: M_b                         */
+    LLOID_Q_STRIDE = 7,              /* strides pushed so far                     */
+    LLOID_Q_N_SLICES = 8,            /* slices over all banks                     */
+    LLOID_Q_SLICE_LOOKAHEAD = 9,     /* index = global slice: look-ahead samples  */
+    LLOID_Q_FLOPS_PER_STRIDE = 10,   /* algorithmic flops of one stride           */
+    LLOID_Q_DEVICE_BYTES = 11        /* device memory the plan holds              */
+} lloid_query;
+
+lloid_status lloid_plan_query(const lloid_plan *plan, int32_t what, int32_t index, int64_t *value);
+
+/* Filter the next stride.
+ *   strain_dev  device, [n_det][F] float32: whitened strain of this stride
+ *   gap_mask    bit d set: detector d's stride is a gap and is taken as zeros
+ *   snr_dev     device or NULL.  If not NULL, receives for every bank b the
+ *               block [n_det][M_b][F][2] float32 at LLOID_Q_BANK_SERIES_OFFSET:
+ *               interleaved (re, im) of z_i at top-rate samples kF..kF+F-1
+ *   peaks_dev   device, receives for every bank b the block [n_det][M_b] of
+ *               lloid_peak at LLOID_Q_BANK_PEAK_OFFSET
+ * All buffers are caller-owned and must stay valid until the work enqueued
+ * on `stream` completes.  Strides must be pushed in order.
+ * Errors: LLOID_E_ARG (NULL strain or peaks), LLOID_E_HIP. */
+lloid_status lloid_push_stride(lloid_plan *plan, const float *strain_dev, uint32_t gap_mask,
+                               float *snr_dev, lloid_peak *peaks_dev, void *stream);
+
+/* Zero all history and restart at stride 0. */
+lloid_status lloid_reset(lloid_plan *plan, void *stream);
+
+/* Streaming state (all history buffers and the stride counter) as an opaque
+ * blob: size in bytes, save to a host buffer, load from one saved by a plan
+ * created with the same banks and config.  Save and load synchronise
+ * `stream`.  Errors: LLOID_E_ARG, LLOID_E_STATE (blob from another plan
+ * layout), LLOID_E_HIP. */
+lloid_status lloid_state_size(const lloid_plan *plan, size_t *bytes);
+lloid_status lloid_state_save(lloid_plan *plan, void *host_dst, size_t bytes, void *stream);
+lloid_status lloid_state_load(lloid_plan *plan, const void *host_src, size_t bytes, void *stream);
+
+/* Internal streams, for stage-by-stage checks.  Copies samples [m_lo, m_hi)
+ * (absolute indices at the stream's rate) of detector `det` into the host
+ * buffer `dst` (float32, m_hi - m_lo values per row):
+ *   LLOID_INSPECT_DOWNSAMPLED  index = decimation factor D (1 = input
+ *                              strain); one row
+ *   LLOID_INSPECT_BASIS_OUT    index = global slice (banks in order, slices
+ *                              in order); L^s rows of y^s_l
+ * Only samples still held in the history are available
+ * (LLOID_E_STATE otherwise).  Synchronises `stream`. */
+typedef enum { LLOID_INSPECT_DOWNSAMPLED = 0, LLOID_INSPECT_BASIS_OUT = 1 } lloid_inspect_what;
+lloid_status lloid_inspect(lloid_plan *plan, int32_t what, int32_t index, int32_t det,
+                           int64_t m_lo, int64_t m_hi, float *dst, void *stream);
+
+/* Per-kernel timing of lloid_push_stride with HIP events recorded on the
+ * call's stream around each of the stride's kernels:
+ *   0 ingest, 1 decimation, 2 basis correlation, 3 split reduction,
+ *   4 mixing + upsample-and-add + series + peak candidates, 5 triggers.
+ * lloid_profile_enable(plan, 1) starts a new accumulation (0 stops it);
+ * lloid_profile_read synchronises the recorded events and returns the
+ * summed duration (ms) and the number of launches of one kernel since the
+ * accumulation started.  Errors: LLOID_E_ARG, LLOID_E_HIP. */
+typedef enum {
+    LLOID_K_INGEST = 0, LLOID_K_DOWN = 1, LLOID_K_CORR = 2,
+    LLOID_K_REDUCE = 3, LLOID_K_MIX = 4, LLOID_K_PEAKS = 5, LLOID_K_COUNT = 6
+} lloid_kernel_id;
+lloid_status lloid_profile_enable(lloid_plan *plan, int32_t enable);
+lloid_status lloid_profile_read(lloid_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);
+
+const char *lloid_status_string(lloid_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LLOID_H */

@@ -1,0 +1,128 @@
+// Internal layout shared by the host plan (lloid_plan.hip) and the device
+// kernels (lloid_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lloid.h"
+
+namespace lloid {
+
+// ---------------------------------------------------------------- constants
+constexpr int kMaxLevels = 12;        // distinct rates per bank (top included)
+constexpr int kMaxBasis = 160;        // L^s limit, and per bank and rate (ABI)
+constexpr int kCorrTQ = 64;           // correlation tile: output columns
+constexpr int kCorrTK = 64;           // correlation tile: taps staged per step
+constexpr int kCorrSplitK = 1024;     // taps per correlation work item
+constexpr int kMixTM = 32;            // mixing tile: real rows (16 templates)
+constexpr int kMixTN = 256;           // mixing tile: top-rate samples
+constexpr int kUpTaps = 17;           // 2 N_up + 1 taps per polyphase branch
+
+// -------------------------------------------------------------- work items
+// Basis correlation (Sec. II.C.2 "Filtering and reconstruction"):
+//   y_l[q] = sum_n u_l[n] d[q + n + off],  off = -delay - (N-1)
+// for the f new columns q = k f + la + c, c in [col0, col0+ncols), taps
+// n in [k0, k0+klen).  The partial result goes to part[l * f + c].
+struct CorrItem {
+    const float *U;          // [Lpad][Npad] fp32 (FP32 mode)
+    const void *Uhi;         // reduced-precision basis, [Lpad][Npad]
+    const void *Ulo;         // low part (BF16X3) or nullptr
+    const float *ring;       // stream at the slice rate for this detector (mirror ring)
+    float *part;             // partial [Lpad][f] for this split
+    const float *uscale;     // FP8: per-row scale or nullptr
+    int64_t off;             // la - delay - (N - 1)  (index = k f + off + c + n)
+    int32_t Npad, Lpad, cap, f;
+    int32_t col0, ncols, k0, klen;
+    int32_t mb;              // Lpad / 16
+    int32_t pad_;
+};
+
+// Deterministic split-K reduction into the basis-output ring.
+struct ReduceItem {
+    const float *part;       // [nsplit][Lpad][f]
+    float *yring;            // [Lpad][2 capY] mirror ring
+    int32_t nsplit, L, Lpad, f, capY, la;
+};
+
+// Decimation (Eq. (sinc) kernel, zero phase): d_D[m] = sum_t g[t] x[D m + t - c]
+// for m in [k f - n_down + m0, ... + chunk).
+struct DownItem {
+    const float *xring;      // top-rate mirror ring of this detector
+    float *dring;            // output mirror ring at rate F/D
+    const float *taps;       // 2c+1 taps
+    int32_t D, c, f, m0, chunk, capx, capd, n_down;
+};
+
+// Mixing + upsample-and-add (Sec. II.C.2 "Upsampling", "Combining", Sec. II.C.3).
+struct MixSlice {
+    const float *W;          // [2M][Lpad] fp32 normalised mixing rows
+    const void *Whi;         // reduced precision
+    const void *Wlo;
+    const float *Y;          // basis-output ring of detector 0 [Lpad][2 capY]
+    int64_t ydet;            // floats between detectors' rings
+    int32_t L, Lpad, capY, level;
+};
+
+struct MixBank {
+    int32_t M;               // complex templates
+    int32_t nlev;            // levels 0..nlev-1 (0 = top rate)
+    int32_t rate[kMaxLevels];
+    int32_t P[kMaxLevels];       // decimation of the level w.r.t. the top rate
+    int32_t p[kMaxLevels];       // p[j] = rate[j-1] / rate[j] (j >= 1)
+    int32_t lo[kMaxLevels];      // window start of tile t0 = 0, local index
+    int32_t n[kMaxLevels];       // window length
+    int32_t up_off[kMaxLevels];  // offset of level j's sub-kernels in the tap table
+    int32_t slice_begin[kMaxLevels + 1];  // MixSlice range per level
+    int64_t series_off;          // float offset of the bank's series block
+    int64_t peak_off;            // entry offset of the bank's peak block
+    int64_t part_off;            // offset of the bank's partial peaks
+    int32_t n_ttiles;
+    int32_t pad_;
+};
+
+struct MixItem {
+    int32_t bank, det, r0, t0;
+};
+
+struct PartialPeak {
+    float p2;                // max |z|^2
+    int32_t idx;             // in-stride index
+    float re, im;
+};
+
+struct PeakItem {
+    int64_t part_off;        // first partial of this bank/detector
+    int64_t peak_off;        // first output entry
+    int32_t M, n_ttiles;
+};
+
+// ---------------------------------------------------------------- launches
+struct LaunchCtx {
+    hipStream_t stream;
+    const int64_t *stride_ctr;   // device stride counter
+};
+
+hipError_t launch_ingest(const LaunchCtx &, const float *strain, uint32_t gap_mask, float *xring,
+                         int64_t ring_det_stride, int32_t cap, int32_t F, int32_t n_det);
+hipError_t launch_down(const LaunchCtx &, const DownItem *items, int32_t n_items, int32_t max_lds_floats);
+hipError_t launch_corr(const LaunchCtx &, int precision, const CorrItem *items, int32_t n_items);
+hipError_t launch_reduce(const LaunchCtx &, const ReduceItem *items, int32_t n_items, int32_t max_rows);
+hipError_t launch_mix(const LaunchCtx &, int precision, const MixItem *items, int32_t n_items,
+                      const MixBank *banks, const MixSlice *slices, const float *uptaps,
+                      float *series, PartialPeak *partials, int32_t F, int32_t n_det,
+                      int32_t S, int32_t SW, int32_t nup);
+hipError_t launch_peaks(const LaunchCtx &, const PeakItem *items, int32_t n_items,
+                        const PartialPeak *partials, lloid_peak *peaks, float threshold,
+                        int64_t *stride_ctr_advance);
+hipError_t launch_normalize(hipStream_t, const double *const *W64, const int32_t *Ls,
+                            int32_t n_slices, int32_t rows, int32_t normalize, double *inv_norm);
+hipError_t launch_convert_rows(hipStream_t, const double *src, int32_t rows, int32_t cols,
+                               int32_t src_ld, const double *row_scale, int precision, int role,
+                               float *dst32, void *dst_hi, void *dst_lo, int32_t dst_ld,
+                               float *row_scale_out);
+
+// roles for launch_convert_rows
+enum { ROLE_BASIS = 0, ROLE_MIXING = 1 };
+
+}  // namespace lloid

@@ -1,0 +1,765 @@
+// Host side of the LLOID C ABI: plan construction, work tables, stride driver.
+//
+// Plan construction validates every bank, groups each bank's slices by rate
+// into a chain of levels (top rate first; Sec. II.C.1 slices, Sec. II.C.3
+// "Multidimensional filtering" groups by rate), derives the integer
+// look-ahead of every level from the polyphase index ranges (the cumulative
+// upsampling half-lengths of the pre-synchronisation equation, Sec. II.C.3),
+// checks that every slice delay covers it plus the decimator half-length,
+// sizes the history rings, builds the work tables of the six per-stride
+// kernels, and moves the bank to the device (FP64 normalisation there).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "lloid_internal.h"
+
+using namespace lloid;
+
+#define HIP_OK(expr)                                   \
+    do {                                               \
+        hipError_t e_ = (expr);                        \
+        if (e_ != hipSuccess) return LLOID_E_HIP;      \
+    } while (0)
+
+namespace {
+
+constexpr uint64_t kStateMagic = 0x4c4c4f4944535431ull;   // "LLOIDST1"
+
+int ilog2(int v) {
+    int r = 0;
+    while ((1 << r) < v) ++r;
+    return r;
+}
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
+int64_t floordiv(int64_t a, int64_t b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+// Eq. (sinc): g[k] = sinc((k-c)/f) sinc((k-c)/c), k = 0..2c.
+double sinc_pi(double x) { return x == 0.0 ? 1.0 : std::sin(M_PI * x) / (M_PI * x); }
+std::vector<double> sinc_windowed_sinc(int f, int c) {
+    std::vector<double> g(2 * c + 1);
+    for (int k = 0; k <= 2 * c; ++k) {
+        const double u = k - c;
+        g[k] = sinc_pi(u / f) * sinc_pi(u / c);
+    }
+    return g;
+}
+
+struct Ring {
+    float *base = nullptr;   // n_det rings of 2*cap floats
+    int32_t cap = 0;
+    int64_t det_stride = 0;
+    int64_t need = 0;        // required span (samples)
+};
+
+struct PSlice {
+    int bank, rate, D, level, N, L, Npad, Lpad, la, nsplit, capY;
+    int64_t delay;
+    float *U32 = nullptr;
+    float *W32 = nullptr;
+    void *Uhi = nullptr, *Ulo = nullptr, *Whi = nullptr, *Wlo = nullptr;
+    float *uscale = nullptr;
+    float *yring = nullptr;  // n_det rings of [Lpad][2 capY]
+    int64_t ydet = 0;
+    float *part = nullptr;   // n_det x [nsplit][Lpad][f]
+    int64_t part_det = 0;
+};
+
+struct PBank {
+    int M, nlev, rows_pad;
+    std::vector<int> rates, la;
+    std::vector<int> slices;   // plan slice ids, sorted by level
+    int64_t series_off, peak_off, part_off;
+};
+
+}  // namespace
+
+struct lloid_plan {
+    lloid_config cfg{};
+    int F = 0, n_det = 0, nup = 8, ndown = 32, precision = 0;
+    int64_t stride = 0;
+    std::vector<PSlice> slices;
+    std::vector<PBank> banks;
+    std::map<int, Ring> rings;     // by decimation factor D (1 = strain)
+    std::vector<void *> allocs;
+    size_t device_bytes = 0;
+
+    CorrItem *d_corr = nullptr;
+    int n_corr = 0;
+    ReduceItem *d_reduce = nullptr;
+    int n_reduce = 0, reduce_rows = 0;
+    DownItem *d_down = nullptr;
+    int n_downitems = 0, down_lds = 0;
+    MixItem *d_mix = nullptr;
+    int n_mix = 0;
+    MixBank *d_mbanks = nullptr;
+    MixSlice *d_mslices = nullptr;
+    int mixS = 0, mixSW = 0;
+    PeakItem *d_peakitems = nullptr;
+    int n_peakitems = 0;
+    PartialPeak *d_partials = nullptr;
+    float *d_uptaps = nullptr;
+    int64_t *d_stride = nullptr;
+    int64_t series_floats = 0, n_peaks = 0, total_templates = 0;
+    double flops = 0.0;
+
+    // per-kernel event timing (lloid_profile_*)
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_kernel;
+    double prof_ms[LLOID_K_COUNT] = {0};
+    int64_t prof_n[LLOID_K_COUNT] = {0};
+
+    template <typename T>
+    lloid_status alloc(T **p, size_t count, bool zero = true) {
+        void *q = nullptr;
+        const size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+        if (hipMalloc(&q, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return LLOID_E_NOMEM;
+        }
+        allocs.push_back(q);
+        device_bytes += bytes;
+        if (zero && hipMemset(q, 0, bytes) != hipSuccess) return LLOID_E_HIP;
+        *p = static_cast<T *>(q);
+        return LLOID_OK;
+    }
+    ~lloid_plan() {
+        for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+        for (void *p : allocs) (void)hipFree(p);
+    }
+    // events bracketing one kernel launch when profiling
+    hipError_t mark(int kernel, hipStream_t st, bool begin) {
+        if (!profiling) return hipSuccess;
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t e;
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return r;
+            ev_pool.push_back(e);
+        }
+        if (begin) ev_kernel.push_back(kernel);
+        return hipEventRecord(ev_pool[ev_used++], st);
+    }
+};
+
+#define ST_OK(expr)                              \
+    do {                                         \
+        lloid_status s_ = (expr);                \
+        if (s_ != LLOID_OK) return s_;           \
+    } while (0)
+
+namespace {
+
+template <typename T>
+lloid_status upload(lloid_plan *P, T **dst, const std::vector<T> &v, hipStream_t st) {
+    ST_OK(P->alloc(dst, v.size(), false));
+    if (!v.empty()) HIP_OK(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return LLOID_OK;
+}
+
+lloid_status validate(const lloid_config *c, const lloid_bank *banks, int32_t n_banks) {
+    if (!c || !banks || n_banks < 1) return LLOID_E_ARG;
+    if (c->sample_rate_hz <= 0 || c->sample_rate_hz % kMixTN) return LLOID_E_SHAPE;
+    if (c->n_detectors < 1 || c->n_detectors > 32) return LLOID_E_ARG;
+    if (c->n_down < 1 || c->n_down > 64 || c->n_up < 1 || c->n_up > 8) return LLOID_E_ARG;
+    if (c->precision < LLOID_FP32 || c->precision > LLOID_FP8_BF16) return LLOID_E_ARG;
+    if (!std::isfinite(c->snr_threshold)) return LLOID_E_ARG;
+    for (int b = 0; b < n_banks; ++b) {
+        const lloid_bank &B = banks[b];
+        if (B.n_templates < 1 || B.n_slices < 1 || !B.slices) return LLOID_E_ARG;
+        for (int s = 0; s < B.n_slices; ++s) {
+            const lloid_slice &S = B.slices[s];
+            if (!S.basis || !S.mixing) return LLOID_E_ARG;
+            if (S.rate_hz <= 0 || c->sample_rate_hz % S.rate_hz) return LLOID_E_SHAPE;
+            const int D = c->sample_rate_hz / S.rate_hz;
+            if (!is_pow2(D)) return LLOID_E_SHAPE;
+            if (D > 64) return LLOID_E_UNSUPPORTED;
+            if (S.n_taps < 1 || S.n_basis < 1 || S.delay < 0) return LLOID_E_SHAPE;
+            if (S.n_basis > kMaxBasis) return LLOID_E_UNSUPPORTED;
+        }
+    }
+    return LLOID_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lloid_status_string(lloid_status s) {
+    switch (s) {
+        case LLOID_OK: return "ok";
+        case LLOID_E_ARG: return "invalid argument";
+        case LLOID_E_SHAPE: return "inconsistent shapes or rates";
+        case LLOID_E_LATENCY: return "slice delay shorter than its resampling look-ahead";
+        case LLOID_E_NOMEM: return "out of device or host memory";
+        case LLOID_E_HIP: return "HIP runtime error";
+        case LLOID_E_STATE: return "invalid plan state for this call";
+        case LLOID_E_UNSUPPORTED: return "unsupported by this build";
+    }
+    return "unknown status";
+}
+
+lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *banks, int32_t n_banks, void *stream,
+                               lloid_plan **out) {
+    if (!out) return LLOID_E_ARG;
+    *out = nullptr;
+    ST_OK(validate(config, banks, n_banks));
+    if (config->precision == LLOID_FP8_BF16) return LLOID_E_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+
+    lloid_plan *P = new (std::nothrow) lloid_plan();
+    if (!P) return LLOID_E_NOMEM;
+    struct Guard {
+        lloid_plan *p;
+        ~Guard() { delete p; }
+    } guard{P};
+
+    P->cfg = *config;
+    P->F = config->sample_rate_hz;
+    P->n_det = config->n_detectors;
+    P->nup = config->n_up;
+    P->ndown = config->n_down;
+    P->precision = config->precision;
+    const int F = P->F, ND = P->n_det, nup = P->nup, ndown = P->ndown;
+
+    // ---------------------------------------------------------- chains
+    int64_t series_off = 0, peak_off = 0, part_off = 0;
+    const int n_ttiles = F / kMixTN;
+    for (int b = 0; b < n_banks; ++b) {
+        const lloid_bank &B = banks[b];
+        PBank pb;
+        pb.M = B.n_templates;
+        pb.rows_pad = (int)round_up(2 * (int64_t)B.n_templates, kMixTM);
+        std::vector<int> rates{F};
+        for (int s = 0; s < B.n_slices; ++s) rates.push_back(B.slices[s].rate_hz);
+        std::sort(rates.begin(), rates.end(), std::greater<int>());
+        rates.erase(std::unique(rates.begin(), rates.end()), rates.end());
+        if ((int)rates.size() > kMaxLevels) return LLOID_E_UNSUPPORTED;
+        pb.rates = rates;
+        pb.nlev = (int)rates.size();
+        // look-ahead per level: window of stride 0 is [-la_j, f_j + la_j)
+        pb.la.assign(pb.nlev, 0);
+        int64_t hi = F;
+        for (int j = 1; j < pb.nlev; ++j) {
+            const int p = rates[j - 1] / rates[j];
+            hi = floordiv(hi - 1, p) + nup + 1;
+            pb.la[j] = (int)(hi - rates[j]);
+        }
+        std::vector<int> lsum(pb.nlev, 0);
+        for (int s = 0; s < B.n_slices; ++s) {
+            const lloid_slice &S = B.slices[s];
+            PSlice ps{};
+            ps.bank = b;
+            ps.rate = S.rate_hz;
+            ps.D = F / S.rate_hz;
+            ps.level = (int)(std::find(rates.begin(), rates.end(), S.rate_hz) - rates.begin());
+            ps.N = S.n_taps;
+            ps.L = S.n_basis;
+            ps.Npad = (int)round_up(S.n_taps, kCorrTK);
+            ps.Lpad = (int)round_up(S.n_basis, 16);
+            ps.la = pb.la[ps.level];
+            ps.delay = S.delay;
+            ps.nsplit = (int)((ps.Npad + kCorrSplitK - 1) / kCorrSplitK);
+            const int f = S.rate_hz;
+            ps.capY = f + 2 * ps.la + 16;
+            // pre-synchronisation: the newest sample the slice reads must be
+            // available at the end of the stride
+            const int64_t need = ps.la + (ps.D > 1 ? ndown : 0);
+            if (S.delay < need) return LLOID_E_LATENCY;
+            lsum[ps.level] += ps.Lpad;
+            if (lsum[ps.level] > kMaxBasis) return LLOID_E_UNSUPPORTED;
+            pb.slices.push_back((int)P->slices.size());
+            P->slices.push_back(ps);
+        }
+        std::stable_sort(pb.slices.begin(), pb.slices.end(),
+                         [&](int a, int c) { return P->slices[a].level < P->slices[c].level; });
+        pb.series_off = series_off;
+        pb.peak_off = peak_off;
+        pb.part_off = part_off;
+        series_off += (int64_t)ND * pb.M * F * 2;
+        peak_off += (int64_t)ND * pb.M;
+        part_off += (int64_t)ND * pb.M * n_ttiles;
+        P->banks.push_back(pb);
+        P->total_templates += pb.M;
+    }
+    P->series_floats = series_off;
+    P->n_peaks = peak_off;
+
+    // ---------------------------------------------------------- rings
+    int Dmax = 1;
+    for (auto &s : P->slices) Dmax = std::max(Dmax, s.D);
+    P->rings[1].need = F + 2LL * Dmax * ndown + 1;
+    for (auto &s : P->slices) {
+        Ring &r = P->rings[s.D];
+        const int f = s.rate;
+        const int64_t span = (s.D > 1) ? (int64_t)f - ndown + s.delay + s.N - 1 - s.la : (int64_t)F + s.delay + s.N - 1;
+        r.need = std::max(r.need, std::max<int64_t>(span, f));
+    }
+    for (auto &kv : P->rings) {
+        Ring &r = kv.second;
+        if (r.need + 64 > INT32_MAX / 2) return LLOID_E_UNSUPPORTED;
+        r.cap = (int32_t)round_up(r.need + 64, 64);
+        r.det_stride = 2LL * r.cap;
+        ST_OK(P->alloc(&r.base, (size_t)ND * r.det_stride));
+    }
+
+    // ---------------------------------------------------------- device bank
+    // FP64 staging, normalisation (per bank, over all its slices), conversion
+    {
+        std::vector<double *> w64(P->slices.size(), nullptr);
+        size_t max_u = 0;
+        for (auto &s : P->slices) max_u = std::max(max_u, (size_t)s.L * s.N);
+        double *u64 = nullptr;
+        ST_OK(P->alloc(&u64, max_u, false));
+        for (int b = 0; b < n_banks; ++b) {
+            const lloid_bank &B = banks[b];
+            PBank &pb = P->banks[b];
+            const int rows = 2 * pb.M;
+            std::vector<int32_t> Ls;
+            std::vector<const double *> wp;
+            int sidx0 = -1;
+            for (int s = 0; s < B.n_slices; ++s) {
+                const int id = (int)(std::find_if(P->slices.begin(), P->slices.end(),
+                                                  [&](const PSlice &x) { return x.bank == b; }) -
+                                     P->slices.begin()) + s;
+                if (sidx0 < 0) sidx0 = id;
+                PSlice &ps = P->slices[id];
+                ST_OK(P->alloc(&w64[id], (size_t)rows * ps.L, false));
+                HIP_OK(hipMemcpyAsync(w64[id], B.slices[s].mixing, sizeof(double) * rows * ps.L,
+                                      hipMemcpyHostToDevice, st));
+                Ls.push_back(ps.L);
+                wp.push_back(w64[id]);
+            }
+            const double **d_wp = nullptr;
+            int32_t *d_Ls = nullptr;
+            double *inv = nullptr;
+            ST_OK(upload(P, &d_wp, wp, st));
+            ST_OK(upload(P, &d_Ls, Ls, st));
+            ST_OK(P->alloc(&inv, rows, false));
+            HIP_OK(launch_normalize(st, d_wp, d_Ls, (int32_t)Ls.size(), rows, P->cfg.normalize, inv));
+            for (int s = 0; s < B.n_slices; ++s) {
+                const int id = sidx0 + s;
+                PSlice &ps = P->slices[id];
+                // mixing rows [rows_pad][Lpad]
+                ST_OK(P->alloc(&ps.W32, (size_t)pb.rows_pad * ps.Lpad));
+                HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, LLOID_FP32, ROLE_MIXING, ps.W32,
+                                           nullptr, nullptr, ps.Lpad, nullptr));
+                // basis [Lpad][Npad]
+                HIP_OK(hipMemcpyAsync(u64, B.slices[s].basis, sizeof(double) * ps.L * ps.N, hipMemcpyHostToDevice,
+                                      st));
+                ST_OK(P->alloc(&ps.U32, (size_t)ps.Lpad * ps.Npad));
+                HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, LLOID_FP32, ROLE_BASIS, ps.U32,
+                                           nullptr, nullptr, ps.Npad, nullptr));
+                HIP_OK(hipStreamSynchronize(st));   // u64 staging is reused
+            }
+        }
+        HIP_OK(hipStreamSynchronize(st));
+    }
+
+    // ---------------------------------------------------------- per-slice buffers
+    for (auto &s : P->slices) {
+        s.ydet = (int64_t)s.Lpad * 2 * s.capY;
+        ST_OK(P->alloc(&s.yring, (size_t)ND * s.ydet));
+        s.part_det = (int64_t)s.nsplit * s.Lpad * s.rate;
+        ST_OK(P->alloc(&s.part, (size_t)ND * s.part_det, false));
+    }
+
+    // ---------------------------------------------------------- resampler taps
+    {
+        std::vector<float> up((size_t)(256 - 1 + 256) * kUpTaps, 0.0f);
+        for (int p = 2; p <= 256; p *= 2) {
+            const int c = p * nup;
+            const std::vector<double> g = sinc_windowed_sinc(p, c);
+            float *z = up.data() + (size_t)(p - 1) * kUpTaps;
+            for (int ph = 0; ph < p; ++ph)
+                for (int t = 0; t <= 2 * nup; ++t) {
+                    const int idx = t * p + ph;
+                    z[ph * kUpTaps + t] = idx <= 2 * c ? (float)g[idx] : 0.0f;
+                }
+        }
+        ST_OK(upload(P, &P->d_uptaps, up, st));
+    }
+    std::map<int, float *> dtaps;
+    for (auto &kv : P->rings) {
+        const int D = kv.first;
+        if (D == 1) continue;
+        const int c = D * ndown;
+        std::vector<double> g = sinc_windowed_sinc(D, c);
+        double sum = 0.0;
+        for (double v : g) sum += v;
+        std::vector<float> gf(g.size());
+        for (size_t i = 0; i < g.size(); ++i) gf[i] = (float)(std::sqrt((double)D) * g[i] / sum);
+        float *d = nullptr;
+        ST_OK(upload(P, &d, gf, st));
+        dtaps[D] = d;
+    }
+
+    // ---------------------------------------------------------- work tables
+    {
+        std::vector<DownItem> items;
+        int lds = 0;
+        const Ring &xr = P->rings[1];
+        for (auto &kv : P->rings) {
+            const int D = kv.first;
+            if (D == 1) continue;
+            const Ring &dr = kv.second;
+            const int f = F / D;
+            const int chunk = std::min(256, f);
+            const int c = D * ndown;
+            const int seg = (chunk - 1) * D + 2 * c + 1;
+            lds = std::max(lds, 2 * c + 1 + seg + (seg >> 5) + 1);
+            for (int det = 0; det < ND; ++det)
+                for (int m0 = 0; m0 < f; m0 += chunk)
+                    items.push_back(DownItem{xr.base + det * xr.det_stride, dr.base + det * dr.det_stride, dtaps[D],
+                                             D, c, f, m0, std::min(chunk, f - m0), xr.cap, dr.cap, ndown});
+        }
+        if (lds * 4 > 64 * 1024) return LLOID_E_UNSUPPORTED;
+        P->down_lds = lds;
+        P->n_downitems = (int)items.size();
+        ST_OK(upload(P, &P->d_down, items, st));
+    }
+    {
+        std::vector<CorrItem> items;
+        std::vector<ReduceItem> red;
+        for (auto &s : P->slices) {
+            const Ring &r = P->rings[s.D];
+            const int f = s.rate;
+            for (int det = 0; det < ND; ++det) {
+                for (int sp = 0; sp < s.nsplit; ++sp) {
+                    const int k0 = sp * kCorrSplitK;
+                    const int klen = std::min(kCorrSplitK, s.Npad - k0);
+                    for (int c0 = 0; c0 < f; c0 += kCorrTQ) {
+                        CorrItem it{};
+                        it.U = s.U32;
+                        it.Uhi = s.Uhi;
+                        it.Ulo = s.Ulo;
+                        it.ring = r.base + det * r.det_stride;
+                        it.part = s.part + det * s.part_det + (int64_t)sp * s.Lpad * f;
+                        it.uscale = s.uscale;
+                        it.off = (int64_t)s.la - s.delay - (s.N - 1);
+                        it.Npad = s.Npad;
+                        it.Lpad = s.Lpad;
+                        it.cap = r.cap;
+                        it.f = f;
+                        it.col0 = c0;
+                        it.ncols = std::min(kCorrTQ, f - c0);
+                        it.k0 = k0;
+                        it.klen = klen;
+                        it.mb = s.Lpad / 16;
+                        items.push_back(it);
+                    }
+                }
+                red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L, s.Lpad, f,
+                                         s.capY, s.la});
+                P->reduce_rows = std::max(P->reduce_rows, s.L);
+            }
+            // algorithmic flops: correlation and mixing contractions
+            P->flops += (double)ND * (2.0 * s.L * s.N * f + 2.0 * 2.0 * P->banks[s.bank].M * s.L * f);
+        }
+        std::stable_sort(items.begin(), items.end(), [](const CorrItem &a, const CorrItem &b) {
+            return (int64_t)a.klen * a.mb * a.ncols > (int64_t)b.klen * b.mb * b.ncols;
+        });
+        P->n_corr = (int)items.size();
+        P->n_reduce = (int)red.size();
+        ST_OK(upload(P, &P->d_corr, items, st));
+        ST_OK(upload(P, &P->d_reduce, red, st));
+    }
+    {
+        std::vector<MixBank> mb;
+        std::vector<MixSlice> ms;
+        std::vector<MixItem> items;
+        std::vector<PeakItem> pk;
+        int S = 0, SW = 0;
+        for (int b = 0; b < n_banks; ++b) {
+            PBank &pb = P->banks[b];
+            MixBank m{};
+            m.M = pb.M;
+            m.nlev = pb.nlev;
+            int64_t lo = 0, hi = kMixTN;
+            for (int j = 0; j < pb.nlev; ++j) {
+                m.rate[j] = pb.rates[j];
+                m.P[j] = F / pb.rates[j];
+                if (j > 0) {
+                    const int p = pb.rates[j - 1] / pb.rates[j];
+                    m.p[j] = p;
+                    lo = floordiv(lo, p) - nup;
+                    hi = floordiv(hi - 1, p) + nup + 1;
+                    S = std::max<int>(S, (int)(hi - lo));
+                    if (p > 256) return LLOID_E_UNSUPPORTED;
+                }
+                m.lo[j] = (int)lo;
+                m.n[j] = (int)(hi - lo);
+            }
+            int lvl_l[kMaxLevels] = {0};
+            int cursor = (int)ms.size();
+            for (int j = 0; j <= pb.nlev; ++j) m.slice_begin[j] = cursor;
+            for (int j = 0; j < pb.nlev; ++j) {
+                m.slice_begin[j] = (int)ms.size();
+                for (int id : pb.slices) {
+                    PSlice &s = P->slices[id];
+                    if (s.level != j) continue;
+                    ms.push_back(MixSlice{s.W32, s.Whi, s.Wlo, s.yring, s.ydet, s.L, s.Lpad, s.capY, s.level});
+                    lvl_l[j] += s.Lpad;
+                }
+            }
+            m.slice_begin[pb.nlev] = (int)ms.size();
+            for (int j = 0; j < pb.nlev; ++j) SW = std::max(SW, lvl_l[j]);
+            m.series_off = pb.series_off;
+            m.peak_off = pb.peak_off;
+            m.part_off = pb.part_off;
+            m.n_ttiles = n_ttiles;
+            mb.push_back(m);
+            for (int det = 0; det < ND; ++det) {
+                for (int r0 = 0; r0 < pb.rows_pad; r0 += kMixTM)
+                    for (int t0 = 0; t0 < F; t0 += kMixTN) items.push_back(MixItem{b, det, r0, t0});
+                pk.push_back(PeakItem{pb.part_off + (int64_t)det * pb.M * n_ttiles, pb.peak_off + (int64_t)det * pb.M,
+                                      pb.M, n_ttiles});
+            }
+            // upsampling flops: non-phase-0 outputs x 2 (2 N_up + 1)
+            for (int j = 1; j < pb.nlev; ++j)
+                P->flops += (double)ND * 2.0 * pb.M * (pb.rates[j - 1] - pb.rates[j]) * 2.0 * (2 * nup + 1);
+        }
+        for (auto &kv : P->rings)
+            if (kv.first > 1) P->flops += (double)ND * (F / kv.first) * 2.0 * (2 * kv.first * ndown + 1);
+        P->mixS = (int)round_up(std::max(S, 1), 32) + 8;    // 8 mod 32
+        P->mixSW = (int)round_up(std::max(SW, 16), 32) + 2;  // 2 mod 32
+        if ((2 * kMixTM * P->mixS + kMixTM * P->mixSW) * 4 > 64 * 1024) return LLOID_E_UNSUPPORTED;
+        P->n_mix = (int)items.size();
+        P->n_peakitems = (int)pk.size();
+        ST_OK(upload(P, &P->d_mbanks, mb, st));
+        ST_OK(upload(P, &P->d_mslices, ms, st));
+        ST_OK(upload(P, &P->d_mix, items, st));
+        ST_OK(upload(P, &P->d_peakitems, pk, st));
+        ST_OK(P->alloc(&P->d_partials, (size_t)std::max<int64_t>(part_off, 1)));
+    }
+    ST_OK(P->alloc(&P->d_stride, 1));
+    HIP_OK(hipStreamSynchronize(st));
+    guard.p = nullptr;
+    *out = P;
+    return LLOID_OK;
+}
+
+void lloid_plan_destroy(lloid_plan *plan) {
+    if (!plan) return;
+    (void)hipDeviceSynchronize();
+    delete plan;
+}
+
+lloid_status lloid_plan_query(const lloid_plan *P, int32_t what, int32_t index, int64_t *value) {
+    if (!P || !value) return LLOID_E_ARG;
+    const int nb = (int)P->banks.size();
+    switch (what) {
+        case LLOID_Q_N_BANKS: *value = nb; return LLOID_OK;
+        case LLOID_Q_TOTAL_TEMPLATES: *value = P->total_templates; return LLOID_OK;
+        case LLOID_Q_SERIES_FLOATS: *value = P->series_floats; return LLOID_OK;
+        case LLOID_Q_N_PEAKS: *value = P->n_peaks; return LLOID_OK;
+        case LLOID_Q_STRIDE: *value = P->stride; return LLOID_OK;
+        case LLOID_Q_N_SLICES: *value = (int64_t)P->slices.size(); return LLOID_OK;
+        case LLOID_Q_FLOPS_PER_STRIDE: *value = (int64_t)P->flops; return LLOID_OK;
+        case LLOID_Q_DEVICE_BYTES: *value = (int64_t)P->device_bytes; return LLOID_OK;
+        default: break;
+    }
+    if (what == LLOID_Q_SLICE_LOOKAHEAD) {
+        if (index < 0 || index >= (int)P->slices.size()) return LLOID_E_ARG;
+        *value = P->slices[index].la;
+        return LLOID_OK;
+    }
+    if (index < 0 || index >= nb) return LLOID_E_ARG;
+    switch (what) {
+        case LLOID_Q_BANK_SERIES_OFFSET: *value = P->banks[index].series_off; return LLOID_OK;
+        case LLOID_Q_BANK_PEAK_OFFSET: *value = P->banks[index].peak_off; return LLOID_OK;
+        case LLOID_Q_BANK_TEMPLATES: *value = P->banks[index].M; return LLOID_OK;
+        default: return LLOID_E_ARG;
+    }
+}
+
+lloid_status lloid_push_stride(lloid_plan *P, const float *strain, uint32_t gap_mask, float *snr, lloid_peak *peaks,
+                               void *stream) {
+    if (!P || !strain || !peaks) return LLOID_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    LaunchCtx ctx{st, P->d_stride};
+    const Ring &xr = P->rings[1];
+    HIP_OK(P->mark(LLOID_K_INGEST, st, true));
+    HIP_OK(launch_ingest(ctx, strain, gap_mask, xr.base, xr.det_stride, xr.cap, P->F, P->n_det));
+    HIP_OK(P->mark(LLOID_K_INGEST, st, false));
+    HIP_OK(P->mark(LLOID_K_DOWN, st, true));
+    HIP_OK(launch_down(ctx, P->d_down, P->n_downitems, P->down_lds));
+    HIP_OK(P->mark(LLOID_K_DOWN, st, false));
+    HIP_OK(P->mark(LLOID_K_CORR, st, true));
+    HIP_OK(launch_corr(ctx, P->precision, P->d_corr, P->n_corr));
+    HIP_OK(P->mark(LLOID_K_CORR, st, false));
+    HIP_OK(P->mark(LLOID_K_REDUCE, st, true));
+    HIP_OK(launch_reduce(ctx, P->d_reduce, P->n_reduce, P->reduce_rows));
+    HIP_OK(P->mark(LLOID_K_REDUCE, st, false));
+    HIP_OK(P->mark(LLOID_K_MIX, st, true));
+    HIP_OK(launch_mix(ctx, P->precision, P->d_mix, P->n_mix, P->d_mbanks, P->d_mslices, P->d_uptaps, snr,
+                      P->d_partials, P->F, P->n_det, P->mixS, P->mixSW, P->nup));
+    HIP_OK(P->mark(LLOID_K_MIX, st, false));
+    HIP_OK(P->mark(LLOID_K_PEAKS, st, true));
+    HIP_OK(launch_peaks(ctx, P->d_peakitems, P->n_peakitems, P->d_partials, peaks, P->cfg.snr_threshold,
+                        P->d_stride));
+    HIP_OK(P->mark(LLOID_K_PEAKS, st, false));
+    P->stride += 1;
+    return LLOID_OK;
+}
+
+static lloid_status profile_collect(lloid_plan *P) {
+    if (P->ev_used == 0) return LLOID_OK;
+    HIP_OK(hipEventSynchronize(P->ev_pool[P->ev_used - 1]));
+    for (size_t i = 0; i < P->ev_kernel.size(); ++i) {
+        float ms = 0.0f;
+        HIP_OK(hipEventElapsedTime(&ms, P->ev_pool[2 * i], P->ev_pool[2 * i + 1]));
+        P->prof_ms[P->ev_kernel[i]] += ms;
+        P->prof_n[P->ev_kernel[i]] += 1;
+    }
+    P->ev_used = 0;
+    P->ev_kernel.clear();
+    return LLOID_OK;
+}
+
+lloid_status lloid_profile_enable(lloid_plan *P, int32_t enable) {
+    if (!P) return LLOID_E_ARG;
+    ST_OK(profile_collect(P));
+    for (int k = 0; k < LLOID_K_COUNT; ++k) {
+        P->prof_ms[k] = 0.0;
+        P->prof_n[k] = 0;
+    }
+    P->profiling = enable != 0;
+    return LLOID_OK;
+}
+
+lloid_status lloid_profile_read(lloid_plan *P, int32_t kernel, double *total_ms, int64_t *launches) {
+    if (!P || !total_ms || !launches || kernel < 0 || kernel >= LLOID_K_COUNT) return LLOID_E_ARG;
+    ST_OK(profile_collect(P));
+    *total_ms = P->prof_ms[kernel];
+    *launches = P->prof_n[kernel];
+    return LLOID_OK;
+}
+
+lloid_status lloid_reset(lloid_plan *P, void *stream) {
+    if (!P) return LLOID_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (auto &kv : P->rings)
+        HIP_OK(hipMemsetAsync(kv.second.base, 0, sizeof(float) * P->n_det * kv.second.det_stride, st));
+    for (auto &s : P->slices) HIP_OK(hipMemsetAsync(s.yring, 0, sizeof(float) * P->n_det * s.ydet, st));
+    HIP_OK(hipMemsetAsync(P->d_stride, 0, sizeof(int64_t), st));
+    HIP_OK(hipStreamSynchronize(st));
+    P->stride = 0;
+    return LLOID_OK;
+}
+
+static size_t state_bytes(const lloid_plan *P) {
+    size_t n = 4 * sizeof(uint64_t);
+    for (auto &kv : P->rings) n += sizeof(float) * P->n_det * kv.second.det_stride;
+    for (auto &s : P->slices) n += sizeof(float) * P->n_det * s.ydet;
+    return n;
+}
+
+static uint64_t layout_tag(const lloid_plan *P) {
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) { h = (h ^ v) * 1099511628211ull; };
+    mix(P->F);
+    mix(P->n_det);
+    for (auto &kv : P->rings) {
+        mix(kv.first);
+        mix(kv.second.cap);
+    }
+    for (auto &s : P->slices) {
+        mix(s.Lpad);
+        mix(s.capY);
+        mix(s.rate);
+    }
+    return h;
+}
+
+lloid_status lloid_state_size(const lloid_plan *P, size_t *bytes) {
+    if (!P || !bytes) return LLOID_E_ARG;
+    *bytes = state_bytes(P);
+    return LLOID_OK;
+}
+
+lloid_status lloid_state_save(lloid_plan *P, void *dst, size_t bytes, void *stream) {
+    if (!P || !dst || bytes < state_bytes(P)) return LLOID_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    uint64_t *h = static_cast<uint64_t *>(dst);
+    h[0] = kStateMagic;
+    h[1] = layout_tag(P);
+    h[2] = (uint64_t)P->stride;
+    h[3] = 0;
+    char *c = static_cast<char *>(dst) + 4 * sizeof(uint64_t);
+    for (auto &kv : P->rings) {
+        const size_t n = sizeof(float) * P->n_det * kv.second.det_stride;
+        HIP_OK(hipMemcpyAsync(c, kv.second.base, n, hipMemcpyDeviceToHost, st));
+        c += n;
+    }
+    for (auto &s : P->slices) {
+        const size_t n = sizeof(float) * P->n_det * s.ydet;
+        HIP_OK(hipMemcpyAsync(c, s.yring, n, hipMemcpyDeviceToHost, st));
+        c += n;
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    return LLOID_OK;
+}
+
+lloid_status lloid_state_load(lloid_plan *P, const void *src, size_t bytes, void *stream) {
+    if (!P || !src || bytes < state_bytes(P)) return LLOID_E_ARG;
+    const uint64_t *h = static_cast<const uint64_t *>(src);
+    if (h[0] != kStateMagic || h[1] != layout_tag(P)) return LLOID_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const char *c = static_cast<const char *>(src) + 4 * sizeof(uint64_t);
+    for (auto &kv : P->rings) {
+        const size_t n = sizeof(float) * P->n_det * kv.second.det_stride;
+        HIP_OK(hipMemcpyAsync(kv.second.base, c, n, hipMemcpyHostToDevice, st));
+        c += n;
+    }
+    for (auto &s : P->slices) {
+        const size_t n = sizeof(float) * P->n_det * s.ydet;
+        HIP_OK(hipMemcpyAsync(s.yring, c, n, hipMemcpyHostToDevice, st));
+        c += n;
+    }
+    const int64_t k = (int64_t)h[2];
+    HIP_OK(hipMemcpyAsync(P->d_stride, &k, sizeof(int64_t), hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    P->stride = k;
+    return LLOID_OK;
+}
+
+lloid_status lloid_inspect(lloid_plan *P, int32_t what, int32_t index, int32_t det, int64_t m_lo, int64_t m_hi,
+                           float *dst, void *stream) {
+    if (!P || !dst || det < 0 || det >= P->n_det || m_hi < m_lo) return LLOID_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_OK(hipStreamSynchronize(st));
+    const int64_t len = m_hi - m_lo;
+    if (what == LLOID_INSPECT_DOWNSAMPLED) {
+        auto itr = P->rings.find(index);
+        if (itr == P->rings.end()) return LLOID_E_ARG;
+        const Ring &r = itr->second;
+        const int f = P->F / index;
+        const int64_t newest = index == 1 ? P->stride * P->F - 1 : P->stride * f - P->ndown - 1;
+        if (m_hi - 1 > newest || m_lo <= newest - r.cap || len > r.cap) return LLOID_E_STATE;
+        const int64_t pos = ((m_lo % r.cap) + r.cap) % r.cap;
+        HIP_OK(hipMemcpy(dst, r.base + det * r.det_stride + pos, sizeof(float) * len, hipMemcpyDeviceToHost));
+        return LLOID_OK;
+    }
+    if (what == LLOID_INSPECT_BASIS_OUT) {
+        if (index < 0 || index >= (int)P->slices.size()) return LLOID_E_ARG;
+        const PSlice &s = P->slices[index];
+        const int64_t newest = P->stride * s.rate + s.la - 1;
+        if (m_hi - 1 > newest || m_lo <= newest - s.capY || len > s.capY) return LLOID_E_STATE;
+        const int64_t pos = ((m_lo % s.capY) + s.capY) % s.capY;
+        for (int l = 0; l < s.L; ++l)
+            HIP_OK(hipMemcpy(dst + l * len, s.yring + det * s.ydet + (int64_t)l * 2 * s.capY + pos,
+                             sizeof(float) * len, hipMemcpyDeviceToHost));
+        return LLOID_OK;
+    }
+    return LLOID_E_ARG;
+}
+
+}  // extern "C"

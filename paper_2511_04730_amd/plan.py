@@ -1,0 +1,181 @@
+"""Python face of the LLOID C ABI: argument marshalling only.
+
+Every step of the filtering runs in liblloid's HIP kernels; torch provides
+device memory (tensors) and the HIP stream the work is enqueued on.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib as L
+
+
+@dataclass
+class PeakArrays:
+    snr: "np.ndarray"
+    index: "np.ndarray"
+    re: "np.ndarray"
+    im: "np.ndarray"
+    above: "np.ndarray"
+
+
+def _stream_handle(stream) -> Optional[int]:
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class LloidPlan:
+    """One plan = a set of banks filtered together, for n_detectors streams.
+
+    banks: sequence of objects with ``n_templates`` and ``slices``; each
+    slice has ``rate``, ``delay``, ``basis`` [L, N] and ``mixing`` [2M, L]
+    (float64 arrays)."""
+
+    def __init__(self, banks: Sequence, sample_rate: int, n_detectors: int = 1, precision: str = "fp32",
+                 normalize: bool = True, n_down: int = 32, n_up: int = 8, snr_threshold: float = 4.0,
+                 stream=None):
+        import torch
+        self.lib = L.load()
+        self.sample_rate = int(sample_rate)
+        self.n_detectors = int(n_detectors)
+        self.precision = precision
+        keep = []
+        cbanks = (L.Bank * len(banks))()
+        for b, bank in enumerate(banks):
+            sl = (L.Slice * len(bank.slices))()
+            for i, s in enumerate(bank.slices):
+                U = np.ascontiguousarray(s.basis, dtype=np.float64)
+                W = np.ascontiguousarray(s.mixing, dtype=np.float64)
+                keep += [U, W]
+                sl[i] = L.Slice(int(s.rate), int(s.delay), U.shape[1], U.shape[0],
+                                U.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                W.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+            keep.append(sl)
+            cbanks[b] = L.Bank(int(bank.n_templates), len(bank.slices), sl)
+        cfg = L.Config(self.sample_rate, self.n_detectors, n_down, n_up, L.PRECISIONS[precision],
+                       1 if normalize else 0, float(snr_threshold))
+        handle = ctypes.c_void_p()
+        st = _stream_handle(stream) if torch.cuda.is_available() else None
+        L.check(self.lib.lloid_plan_create(ctypes.byref(cfg), cbanks, len(banks), st, ctypes.byref(handle)),
+                "lloid_plan_create")
+        self.handle = handle
+        self.n_banks = self.query(L.Q_N_BANKS)
+        self.series_floats = self.query(L.Q_SERIES_FLOATS)
+        self.n_peaks = self.query(L.Q_N_PEAKS)
+        self.bank_templates = [self.query(L.Q_BANK_TEMPLATES, b) for b in range(self.n_banks)]
+        self.bank_series_offset = [self.query(L.Q_BANK_SERIES_OFFSET, b) for b in range(self.n_banks)]
+        self.bank_peak_offset = [self.query(L.Q_BANK_PEAK_OFFSET, b) for b in range(self.n_banks)]
+        self.flops_per_stride = self.query(L.Q_FLOPS_PER_STRIDE)
+
+    def query(self, what: int, index: int = 0) -> int:
+        v = ctypes.c_int64()
+        L.check(self.lib.lloid_plan_query(self.handle, what, index, ctypes.byref(v)), "lloid_plan_query")
+        return int(v.value)
+
+    @property
+    def stride(self) -> int:
+        return self.query(L.Q_STRIDE)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.lloid_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ outputs
+    def new_series(self):
+        import torch
+        return torch.empty(self.series_floats, dtype=torch.float32, device="cuda")
+
+    def new_peaks(self):
+        import torch
+        return torch.empty(self.n_peaks * 5, dtype=torch.int32, device="cuda")
+
+    def push(self, strain, gap_mask: int = 0, series=None, peaks=None, write_series: bool = True, stream=None):
+        """Filter the next stride.  strain: cuda float32 [n_det, F].
+        Returns (series or None, peaks) device tensors (see bank_view /
+        peaks_view for per-bank shapes)."""
+        import torch
+        assert strain.is_cuda and strain.dtype == torch.float32 and strain.is_contiguous()
+        assert tuple(strain.shape) == (self.n_detectors, self.sample_rate)
+        if write_series and series is None:
+            series = self.new_series()
+        if peaks is None:
+            peaks = self.new_peaks()
+        sptr = ctypes.c_void_p(series.data_ptr()) if write_series else None
+        L.check(self.lib.lloid_push_stride(self.handle, ctypes.c_void_p(strain.data_ptr()), int(gap_mask), sptr,
+                                           ctypes.c_void_p(peaks.data_ptr()), _stream_handle(stream)),
+                "lloid_push_stride")
+        return (series if write_series else None), peaks
+
+    def bank_view(self, series, bank: int):
+        """[n_det, M_b, F] complex64 view of one bank's block of a series tensor."""
+        import torch
+        M = self.bank_templates[bank]
+        off = self.bank_series_offset[bank]
+        blk = series[off:off + self.n_detectors * M * self.sample_rate * 2]
+        return torch.view_as_complex(blk.view(self.n_detectors, M, self.sample_rate, 2))
+
+    def peaks_view(self, peaks, bank: int) -> PeakArrays:
+        """Host arrays [n_det, M_b] of one bank's triggers."""
+        M = self.bank_templates[bank]
+        off = self.bank_peak_offset[bank]
+        raw = peaks.view(-1, 5)[off:off + self.n_detectors * M].cpu().numpy()
+        f = raw.view(np.float32)
+        shp = (self.n_detectors, M)
+        return PeakArrays(f[:, 0].reshape(shp).copy(), raw[:, 1].reshape(shp).copy(), f[:, 2].reshape(shp).copy(),
+                          f[:, 3].reshape(shp).copy(), raw[:, 4].reshape(shp).copy())
+
+    # ------------------------------------------------------------ timing
+    def profile(self, enable: bool = True) -> None:
+        """Start (or stop) per-kernel HIP-event timing of push()."""
+        L.check(self.lib.lloid_profile_enable(self.handle, 1 if enable else 0), "lloid_profile_enable")
+
+    def profile_read(self) -> dict:
+        """{kernel name: (total ms, launches)} since profile(True)."""
+        out = {}
+        for k, name in enumerate(L.KERNEL_NAMES):
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            L.check(self.lib.lloid_profile_read(self.handle, k, ctypes.byref(ms), ctypes.byref(n)),
+                    "lloid_profile_read")
+            out[name] = (float(ms.value), int(n.value))
+        return out
+
+    # ------------------------------------------------------------ state
+    def reset(self, stream=None) -> None:
+        L.check(self.lib.lloid_reset(self.handle, _stream_handle(stream)), "lloid_reset")
+
+    def state_save(self, stream=None) -> bytes:
+        n = ctypes.c_size_t()
+        L.check(self.lib.lloid_state_size(self.handle, ctypes.byref(n)), "lloid_state_size")
+        buf = ctypes.create_string_buffer(n.value)
+        L.check(self.lib.lloid_state_save(self.handle, buf, n.value, _stream_handle(stream)), "lloid_state_save")
+        return buf.raw
+
+    def state_load(self, blob: bytes, stream=None) -> None:
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        L.check(self.lib.lloid_state_load(self.handle, buf, len(blob), _stream_handle(stream)), "lloid_state_load")
+
+    def inspect(self, what: int, index: int, det: int, m_lo: int, m_hi: int, rows: int = 1, stream=None):
+        out = np.empty((rows, m_hi - m_lo), dtype=np.float32)
+        L.check(self.lib.lloid_inspect(self.handle, what, index, det, m_lo, m_hi,
+                                       out.ctypes.data_as(ctypes.c_void_p), _stream_handle(stream)),
+                "lloid_inspect")
+        return out
+
+    def downsampled(self, D: int, det: int, m_lo: int, m_hi: int) -> np.ndarray:
+        return self.inspect(L.INSPECT_DOWNSAMPLED, D, det, m_lo, m_hi)[0]
+
+    def basis_out(self, slice_index: int, n_basis: int, det: int, m_lo: int, m_hi: int) -> np.ndarray:
+        return self.inspect(L.INSPECT_BASIS_OUT, slice_index, det, m_lo, m_hi, rows=n_basis)

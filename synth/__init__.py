@@ -423,6 +423,52 @@ def config5(n_banks: int = 800, duration_s: int = 1024, dtype=np.float64) -> Wor
                     batched_banks(5, n_banks, (3, 6), (0.5, 128.0), dtype))
 
 
+CACHE_VERSION = 1
+
+
+def _cache_dir() -> str:
+    import os
+    import tempfile
+    d = os.environ.get("LLOID_SYNTH_CACHE", os.path.join(tempfile.gettempdir(), "lloid_synth_cache"))
+    os.makedirs(d, exist_ok=True)
+    return d
+
+
+def cached_workload(name: str, builder) -> Workload:
+    """Build a workload once per machine: banks are stored as .npz (no
+    pickles) under $LLOID_SYNTH_CACHE (default: the temp directory)."""
+    import json
+    import os
+    path = os.path.join(_cache_dir(), f"{name}-v{CACHE_VERSION}.npz")
+    if os.path.exists(path):
+        with np.load(path, allow_pickle=False) as z:
+            meta = json.loads(str(z["meta"]))
+            banks = []
+            for b, bm in enumerate(meta["banks"]):
+                sl = [Slice(r, d, z[f"U_{b}_{i}"], z[f"W_{b}_{i}"]) for i, (r, d) in enumerate(bm["slices"])]
+                tc = z[f"tc_{b}"] if f"tc_{b}" in z else None
+                banks.append(Bank(bm["M"], sl, None, tc, bm.get("f0")))
+            injs = [Injection(*i) for i in meta["injections"]]
+            return Workload(meta["name"], meta["config"], meta["rate"], meta["n_det"], meta["duration"], banks, injs)
+    w = builder()
+    arrays = {}
+    meta = {"name": w.name, "config": w.config, "rate": w.sample_rate, "n_det": w.n_detectors,
+            "duration": w.duration_s, "banks": [],
+            "injections": [[i.bank, i.template, i.detector, i.merger_sample, i.amplitude] for i in w.injections]}
+    for b, bank in enumerate(w.banks):
+        meta["banks"].append({"M": bank.n_templates, "f0": bank.f0,
+                              "slices": [[s.rate, s.delay] for s in bank.slices]})
+        for i, s in enumerate(bank.slices):
+            arrays[f"U_{b}_{i}"] = s.basis
+            arrays[f"W_{b}_{i}"] = s.mixing
+        if bank.tc is not None:
+            arrays[f"tc_{b}"] = bank.tc
+    tmp = path + f".{os.getpid()}.tmp.npz"
+    np.savez(tmp, meta=json.dumps(meta), **arrays)
+    os.replace(tmp, path)
+    return w
+
+
 def workload_strain(w: Workload, duration_s: Optional[int] = None) -> np.ndarray:
     """Noise plus the workload's injections, float64 [n_det, rate*duration]."""
     n = w.sample_rate * (duration_s if duration_s is not None else w.duration_s)
