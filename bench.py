@@ -7,9 +7,16 @@ every template and detector of the workload, with the strain already
 resident in device memory.  Prints one JSON line.
 
 Workloads (synthetic, seeded; see synth/):
+  batched    2 detectors, 200 uneven sub-banks (~120k templates, 3-7 rates
+             4096..64 Hz, L 20-150, filters 0.5-64 s), 4096 Hz   (default)
   realistic  1 detector, 1024 chirp templates, 5 rates 4096..256 Hz,
-             L = 40/60/80/100/120, strain 4096 s at 4096 Hz (default)
-  plain      1 detector, 64 templates, 2 rates (2048/512 Hz), 32 s
+             L = 40/60/80/100/120
+  plain      1 detector, 64 templates, 2 rates (2048/512 Hz)
+
+The default precision is bf16x3 (BF16 operands, both sides split, FP32
+accumulation); --compare fp32 also times the plain FP32 path on the same
+workload.  The SNR error against the FP64 oracle is measured on a sample of
+banks at one stride in the same run.
 """
 from __future__ import annotations
 
@@ -24,11 +31,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "template SNR-samples/sec per MI355X, batched BF16 vs plain FP32 at SNR err≤1e-3"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "fp16": 2500.0, "fp8_bf16": 5000.0}
-HBM_GBS = 8000.0
+DTYPE = {"fp32": "f32", "bf16x3": "bf16x3", "fp16": "f16x2", "fp8_bf16": "fp8"}
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def workload(name: str):
     import synth
+    if name == "batched":
+        return synth.cached_workload("c3", synth.config3)
     if name == "realistic":
         return synth.cached_workload("c2", synth.config2)
     if name == "plain":
@@ -36,8 +49,9 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def kernel_flops(w, n_det: int) -> dict:
-    """Algorithmic flops per launch of the two contraction kernels."""
+def kernel_flops(w) -> dict:
+    """Algorithmic flops per launch of the two contraction kernels (all
+    banks and detectors)."""
     corr = mix = 0.0
     for bank in w.banks:
         M = bank.n_templates
@@ -47,131 +61,172 @@ def kernel_flops(w, n_det: int) -> dict:
         rates = sorted({s.rate for s in bank.slices} | {w.sample_rate}, reverse=True)
         for hi, lo in zip(rates[:-1], rates[1:]):
             mix += 2.0 * (2 * M) * (hi - lo) * 17
-    return {"corr": corr * n_det, "mix": mix * n_det}
+    return {"corr": corr * w.n_detectors, "mix": mix * w.n_detectors}
 
 
-def cpu_baseline(w, x, first: int, seconds: float, gpu_series=None):
-    """The FP64 oracle on the host cores for a bounded sample of strides."""
+def timed(plan, strides, warmup: int, steps: int, write: bool, profile: bool):
+    import torch
+    series = plan.new_series() if write else None
+    peaks = plan.new_peaks()
+    n = len(strides)
+    for k in range(warmup):
+        plan.push(strides[k % n], series=series, peaks=peaks, write_series=write)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    if profile:
+        plan.profile(True)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for k in range(warmup, warmup + steps):
+        plan.push(strides[k % n], series=series, peaks=peaks, write_series=write)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    prof = plan.profile_read() if profile else None
+    if profile:
+        plan.profile(False)
+    del series, peaks
+    return ms, prof
+
+
+def parity_and_baseline(plan, w, x, strides, k: int, seconds: float):
+    """Oracle (FP64, host cores) on detector 0 for stride k of as many banks
+    as fit in `seconds`; GPU series of the same banks and stride from a fresh
+    run; returns (cpu_baseline dict, max SNR error, banks sampled)."""
     import numpy as np
+    import torch
     from oracle import lloid as O
-    cores = len(os.sched_getaffinity(0))
-    cfg = O.OracleConfig(w.sample_rate)
     F = w.sample_rate
-    done, t0 = 0, time.perf_counter()
-    refs = []
-    while True:
-        k = first + done
-        z, _ = O.lloid_filter(x[0, :(k + 1) * F], w.banks[0], cfg, n_strides=1, first_stride=k)
-        refs.append(z)
-        done += 1
-        el = time.perf_counter() - t0
-        if el >= seconds or done >= 64:
+    plan.reset()
+    series = plan.new_series()
+    peaks = plan.new_peaks()
+    for i in range(k + 1):
+        plan.push(strides[i], series=series, peaks=peaks)
+    torch.cuda.synchronize()
+    cfg = O.OracleConfig(F)
+    cores = len(os.sched_getaffinity(0))
+    err, done_b, samples, t0 = 0.0, 0, 0, time.perf_counter()
+    xd = x[0, :(k + 1) * F]
+    for b, bank in enumerate(w.banks):
+        ts = time.perf_counter()
+        z, _ = O.lloid_filter(xd, bank, cfg, n_strides=1, first_stride=k)
+        samples += bank.n_templates * F
+        done_b += 1
+        zg = plan.bank_view(series, b)[0].cpu().numpy().astype(np.complex128)
+        err = max(err, float((np.abs(zg - z) / np.maximum(np.abs(z), 4.0)).max()))
+        if time.perf_counter() - t0 >= seconds:
             break
-    rate = w.n_templates * F * w.n_detectors * done / el
-    out = {"value": rate, "unit": "SNR-samples/s", "cores": cores, "kind": "oracle",
-           "sample": f"{done} strides ({done} s) from stride {first} of the same workload, float64 NumPy, "
-                     f"BLAS threads = {cores}"}
-    err = None
-    if gpu_series is not None:
-        zr = np.concatenate(refs, axis=1)
-        n = min(zr.shape[1], gpu_series.shape[1])
-        zr, zg = zr[:, :n], gpu_series[:, :n]
-        err = float((np.abs(zg - zr) / np.maximum(np.abs(zr), 4.0)).max())
-    return out, err, done
+    el = time.perf_counter() - t0
+    base = {"value": samples / el, "unit": "SNR-samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"stride {k} of detector 0 for the first {done_b} of {len(w.banks)} banks "
+                      f"({samples} SNR-samples), float64 NumPy, BLAS threads = {cores}"}
+    del series, peaks
+    return base, err, done_b
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2048)
-    ap.add_argument("--warmup", type=int, default=64)
-    ap.add_argument("--workload", default="realistic")
-    ap.add_argument("--precision", default="fp32", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="batched", choices=["batched", "realistic", "plain"])
+    ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
+    ap.add_argument("--compare", default="fp32", help="also time this precision ('' to skip)")
+    ap.add_argument("--graph", type=int, default=1, help="replay one HIP graph per stride")
     ap.add_argument("--peaks-only", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU: the filtering path has no multi-GPU "
                                    "form; run with --gpus 1"}))
         return 2
+    big = args.workload == "batched"
+    steps = args.steps if args.steps is not None else (32 if big else 2048)
+    warmup = args.warmup if args.warmup is not None else (8 if big else 64)
 
     import numpy as np
     import torch
     import synth
     from paper_2511_04730_amd import LloidPlan
 
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 4} bytes read, {n * 4} bytes written")
+        del src, dst
+
     w = workload(args.workload)
     F, ND = w.sample_rate, w.n_detectors
-    n_total = args.warmup + args.steps
-    n_avail = w.duration_s
-    x = synth.workload_strain(w, min(n_total, n_avail))
+    k_par = min(64, w.duration_s - 1)
+    n_str = min(max(warmup + steps, k_par + 1), w.duration_s)
+    x = synth.workload_strain(w, n_str)
     xs = torch.from_numpy(x.astype(np.float32)).cuda()
-    strides = [xs[:, (k % n_avail) * F:((k % n_avail) + 1) * F].contiguous() for k in range(min(n_total, n_avail))]
-
-    plan = LloidPlan(w.banks, F, ND, args.precision)
+    strides = [xs[:, k * F:(k + 1) * F].contiguous() for k in range(n_str)]
+    log(f"workload {w.name}: {w.n_templates} templates, {ND} det, {n_str} strides staged")
     write = not args.peaks_only
-    series = plan.new_series() if write else None
-    peaks = plan.new_peaks()
-    for k in range(args.warmup):
-        plan.push(strides[k % len(strides)], series=series, peaks=peaks, write_series=write)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} strides done", file=sys.stderr, flush=True)
+    kf = kernel_flops(w)
 
-    # timed region: K strides, per-kernel HIP events on the launch stream
-    st = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    plan.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(st)
-    for k in range(args.warmup, n_total):
-        plan.push(strides[k % len(strides)], series=series, peaks=peaks, write_series=write)
-    e1.record(st)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1)
-    prof = plan.profile_read()
-    plan.profile(False)
-    print(f"[bench] timed {args.steps} strides: {ms:.2f} ms (wall {wall * 1e3:.2f} ms)", file=sys.stderr, flush=True)
+    def run(precision: str, profile: bool):
+        plan = LloidPlan(w.banks, F, ND, precision)
+        if args.graph and not profile:
+            plan.set_graph(True)
+        ms, prof = timed(plan, strides, warmup, steps, write, profile)
+        return plan, ms, prof
 
-    samples = w.n_templates * F * ND * args.steps
+    plan, ms, _ = run(args.precision, profile=False)
+    log(f"{args.precision}: {steps} strides in {ms:.2f} ms")
+    samples = w.n_templates * F * ND * steps
     value = samples / (ms / 1e3)
-    kf = kernel_flops(w, ND)
+    # per-kernel HIP-event timing over a second timed region (direct launches)
+    _, ms_p, prof = timed(plan, strides, 0, min(steps, 16), write, True)
     dom = max(("corr", "mix"), key=lambda k: prof[k][0])
     avg_ms = prof[dom][0] / max(prof[dom][1], 1)
     achieved = kf[dom] / (avg_ms / 1e3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     kernel_ms = {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items()}
 
-    # parity sample + CPU baseline: rerun from zero history up to the sample
-    base, err = None, None
-    if not args.no_cpu_baseline and w.n_detectors == 1:
-        first = min(64, len(strides) - 8)
-        plan.reset()
-        zs = []
-        series2 = plan.new_series()
-        for k in range(first + 8):
-            plan.push(strides[k], series=series2, peaks=peaks, write_series=True)
-            if k >= first:
-                zs.append(plan.bank_view(series2, 0)[0].cpu().numpy().astype(np.complex128))
-        torch.cuda.synchronize()
-        base, err, n_cpu = cpu_baseline(w, x, first, args.cpu_seconds, np.concatenate(zs, axis=1))
+    base = err = None
+    if not args.no_cpu_baseline:
+        base, err, nb = parity_and_baseline(plan, w, x, strides, k_par, args.cpu_seconds)
+        log(f"oracle sample: {nb} banks, SNR err {err:.3e}")
+    flops_per_stride = plan.flops_per_stride
+    plan.close()
+    del plan
+    torch.cuda.synchronize()
+
+    compare = None
+    if args.compare and args.compare != args.precision:
+        cplan, cms, _ = run(args.compare, profile=False)
+        cval = samples / (cms / 1e3)
+        cerr = None
+        if not args.no_cpu_baseline:
+            _, cerr, _ = parity_and_baseline(cplan, w, x, strides, k_par, min(args.cpu_seconds, 5.0))
+        compare = {"precision": args.compare, "value": cval, "ms_per_step": cms / steps,
+                   "snr_err": cerr, "speedup": value / cval}
+        log(f"{args.compare}: {steps} strides in {cms:.2f} ms")
+        cplan.close()
 
     out = {
-        "metric": METRIC, "value": value, "unit": "SNR-samples/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {"fp32": "f32", "bf16x3": "bf16x3", "fp16": "f16", "fp8_bf16": "fp8"}[args.precision],
-        "data": "synthetic",
-        "config": {"workload": w.name, "templates": w.n_templates, "detectors": ND,
+        "metric": METRIC, "value": value, "unit": "SNR-samples/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms / steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[args.precision], "data": "synthetic",
+        "config": {"workload": w.name, "banks": len(w.banks), "templates": w.n_templates, "detectors": ND,
                    "rates_hz": sorted({s.rate for b in w.banks for s in b.slices}, reverse=True),
-                   "precision": args.precision, "series_written": write, "stride_s": 1,
-                   "flops_per_stride": plan.flops_per_stride},
+                   "precision": args.precision, "series_written": write, "graph": bool(args.graph),
+                   "stride_s": 1, "flops_per_stride": flops_per_stride},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None},
         "kernel_ms": kernel_ms,
         "snr_err": err,
+        "compare": compare,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

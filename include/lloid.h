@@ -184,6 +184,21 @@ typedef enum { LLOID_INSPECT_DOWNSAMPLED = 0, LLOID_INSPECT_BASIS_OUT = 1 } lloi
 lloid_status lloid_inspect(lloid_plan *plan, int32_t what, int32_t index, int32_t det,
                            int64_t m_lo, int64_t m_hi, float *dst, void *stream);
 
+/* Plan options (lloid_set_option).
+ *   LLOID_OPT_GRAPH  1: lloid_push_stride copies the strain into a
+ *                    plan-owned staging buffer on the call's stream and then
+ *                    replays one captured HIP graph of the stride's kernels
+ *                    (one graph launch per stride; the stride index lives in
+ *                    device memory, so the same graph serves every stride).
+ *                    The graph is captured on first use and again whenever
+ *                    the output pointers or the gap mask change.
+ *                    0 (default): the kernels are launched one by one.
+ *                    While profiling is enabled, kernels are launched one by
+ *                    one regardless.
+ * Errors: LLOID_E_ARG (unknown option or value), LLOID_E_HIP. */
+typedef enum { LLOID_OPT_GRAPH = 0 } lloid_option;
+lloid_status lloid_set_option(lloid_plan *plan, int32_t option, int64_t value);
+
 /* Per-kernel timing of lloid_push_stride with HIP events recorded on the
  * call's stream around each of the stride's kernels:
  *   0 ingest, 1 decimation, 2 basis correlation, 3 split reduction,

@@ -78,6 +78,8 @@ def load() -> ctypes.CDLL:
     lib.lloid_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.lloid_profile_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
+    lib.lloid_set_option.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
+    lib.lloid_set_option.restype = ctypes.c_int
     lib.lloid_status_string.argtypes = [ctypes.c_int]
     lib.lloid_status_string.restype = ctypes.c_char_p
     for name in ("lloid_plan_create", "lloid_plan_query", "lloid_push_stride", "lloid_reset",

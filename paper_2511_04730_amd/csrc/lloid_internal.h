@@ -14,10 +14,11 @@ constexpr int kMaxLevels = 12;        // distinct rates per bank (top included)
 constexpr int kMaxBasis = 160;        // L^s limit, and per bank and rate (ABI)
 constexpr int kCorrTQ = 64;           // correlation tile: output columns
 constexpr int kCorrTK = 64;           // correlation tile: taps staged per step
-constexpr int kCorrSplitK = 1024;     // taps per correlation work item
+constexpr int kCorrSplitK = 512;      // taps per correlation work item
 constexpr int kMixTM = 32;            // mixing tile: real rows (16 templates)
 constexpr int kMixTN = 256;           // mixing tile: top-rate samples
 constexpr int kUpTaps = 17;           // 2 N_up + 1 taps per polyphase branch
+constexpr int kMaxLdsBytes = 96 * 1024;   // dynamic LDS per work group we allow (160 KB on gfx950)
 
 // -------------------------------------------------------------- work items
 // Basis correlation (Sec. II.C.2 "Filtering and reconstruction"):
@@ -115,6 +116,7 @@ hipError_t launch_mix(const LaunchCtx &, int precision, const MixItem *items, in
 hipError_t launch_peaks(const LaunchCtx &, const PeakItem *items, int32_t n_items,
                         const PartialPeak *partials, lloid_peak *peaks, float threshold,
                         int64_t *stride_ctr_advance);
+hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes);
 hipError_t launch_normalize(hipStream_t, const double *const *W64, const int32_t *Ls,
                             int32_t n_slices, int32_t rows, int32_t normalize, double *inv_norm);
 hipError_t launch_convert_rows(hipStream_t, const double *src, int32_t rows, int32_t cols,

@@ -98,13 +98,17 @@ hipError_t launch_down(const LaunchCtx &ctx, const DownItem *items, int32_t n_it
 // in LDS: the basis tile row-major with row stride kCorrTK + 2 (the 16 rows x
 // 2 taps a half-wave reads fall in distinct banks) and the strain segment
 // kCorrTQ + kCorrTK long, from which every lane reads its Hankel entry.
-constexpr int kUS = kCorrTK + 2;
+constexpr int kTKF = 32;             // taps per LDS stage
+constexpr int kUS = kTKF + 2;
 
 template <int MBMAX>
 __global__ __launch_bounds__(256) void corr_f32_kernel(const CorrItem *__restrict__ items,
                                                        const int64_t *__restrict__ stride_ctr) {
-    __shared__ float Us[MBMAX * 16 * kUS];
-    __shared__ float ds[kCorrTQ + kCorrTK];
+    // double-buffered: the next stage's tiles are loaded into registers while
+    // the current stage's MFMAs run from LDS
+    __shared__ float Us[2][MBMAX * 16 * kUS];
+    __shared__ float ds[2][kCorrTQ + kTKF];
+    constexpr int PER = (MBMAX * 16 * (kTKF / 2) + 255) / 256;
     const CorrItem it = items[blockIdx.x];
     const int64_t kstr = *stride_ctr;
     const int tid = threadIdx.x;
@@ -117,26 +121,140 @@ __global__ __launch_bounds__(256) void corr_f32_kernel(const CorrItem *__restric
     for (int m = 0; m < MBMAX; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
-    for (int kk = 0; kk < it.klen; kk += kCorrTK) {
-        __syncthreads();
-        // basis tile: rows x kCorrTK taps, float2 per thread-step
-        for (int e = tid; e < rows * (kCorrTK / 2); e += 256) {
-            const int r = e / (kCorrTK / 2), t2 = e % (kCorrTK / 2);
-            const float2 v = *reinterpret_cast<const float2 *>(it.U + (int64_t)r * it.Npad + it.k0 + kk + 2 * t2);
-            Us[r * kUS + 2 * t2] = v.x;
-            Us[r * kUS + 2 * t2 + 1] = v.y;
+    float2 ureg[PER];
+    float dreg = 0.0f;
+    auto gload = [&](int kk) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < rows * (kTKF / 2)) {
+                const int r = e / (kTKF / 2), t2 = e % (kTKF / 2);
+                ureg[i] = *reinterpret_cast<const float2 *>(it.U + (int64_t)r * it.Npad + it.k0 + kk + 2 * t2);
+            }
         }
         const int64_t p0 = posmod(dbase + kk, it.cap);
-        for (int e = tid; e < kCorrTQ + kCorrTK; e += 256) ds[e] = it.ring[p0 + e];
-        __syncthreads();
+        if (tid < kCorrTQ + kTKF) dreg = it.ring[p0 + tid];
+    };
+    auto lstore = [&](int buf) {
 #pragma unroll
-        for (int ks = 0; ks < kCorrTK; ks += 4) {
-            const float b = ds[wave * 16 + li + ks + lk];
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < rows * (kTKF / 2)) {
+                const int r = e / (kTKF / 2), t2 = e % (kTKF / 2);
+                Us[buf][r * kUS + 2 * t2] = ureg[i].x;
+                Us[buf][r * kUS + 2 * t2 + 1] = ureg[i].y;
+            }
+        }
+        if (tid < kCorrTQ + kTKF) ds[buf][tid] = dreg;
+    };
+    const int nchunks = it.klen / kTKF;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int c = 0; c < nchunks; ++c) {
+        const int buf = c & 1;
+        if (c + 1 < nchunks) gload((c + 1) * kTKF);
+#pragma unroll
+        for (int ks = 0; ks < kTKF; ks += 4) {
+            const float b = ds[buf][wave * 16 + li + ks + lk];
 #pragma unroll
             for (int m = 0; m < MBMAX; ++m) {
                 if (m < it.mb) {
-                    const float a = Us[(m * 16 + li) * kUS + ks + lk];
+                    const float a = Us[buf][(m * 16 + li) * kUS + ks + lk];
                     acc[m] = mfma_16x16x4_f32(a, b, acc[m]);
+                }
+            }
+        }
+        if (c + 1 < nchunks) lstore(buf ^ 1);
+        __syncthreads();
+    }
+    const int c = wave * 16 + li;
+    if (c < it.ncols) {
+#pragma unroll
+        for (int m = 0; m < MBMAX; ++m) {
+            if (m < it.mb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = m * 16 + lk * 4 + v;
+                    it.part[(int64_t)r * it.f + it.col0 + c] = acc[m][v];
+                }
+            }
+        }
+    }
+}
+
+// 16-bit correlation on v_mfma_f32_16x16x32_{bf16,f16}: eight consecutive
+// taps per lane and K-group.  The basis tile is staged row-major with row
+// stride 72 elements (144 B = 16 mod 128, 16-B fragment reads of a half-wave
+// in distinct banks).  A Hankel fragment d[q + n .. q + n + 7] starts at an
+// arbitrary element, so the strain segment is staged as 8 copies shifted by
+// 0..7 elements: the fragment is read from copy (q + n) mod 8 at an aligned
+// offset.  The strain is split on the fly, d = d_hi + d_lo.
+//   SPLIT_U (bf16x3): U_hi d_lo + U_lo d_hi + U_hi d_hi
+//   otherwise (fp16): U d_lo + U d_hi
+template <typename T, typename T8, bool SPLIT_U>
+__global__ __launch_bounds__(256) void corr16_kernel(const CorrItem *__restrict__ items,
+                                                     const int64_t *__restrict__ stride_ctr) {
+    constexpr int TK = 64;
+    constexpr int US = TK + 8;
+    constexpr int MBMAX = kMaxBasis / 16;
+    constexpr int DL = kCorrTQ + TK + 8;
+    __shared__ __attribute__((aligned(16))) T Uh[MBMAX * 16 * US];
+    __shared__ __attribute__((aligned(16))) T Ul[SPLIT_U ? MBMAX * 16 * US : 8];
+    __shared__ __attribute__((aligned(16))) T Dh[8 * DL];
+    __shared__ __attribute__((aligned(16))) T Dl[8 * DL];
+    const CorrItem it = items[blockIdx.x];
+    const int64_t kstr = *stride_ctr;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rows = it.mb * 16;
+    const T *gh = static_cast<const T *>(it.Uhi);
+    const T *gl = static_cast<const T *>(it.Ulo);
+
+    floatx4 acc[MBMAX];
+#pragma unroll
+    for (int m = 0; m < MBMAX; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
+    for (int kk = 0; kk < it.klen; kk += TK) {
+        __syncthreads();
+        for (int e = tid; e < rows * (TK / 8); e += 256) {
+            const int r = e / (TK / 8), c8 = e % (TK / 8);
+            const int64_t g = (int64_t)r * it.Npad + it.k0 + kk + 8 * c8;
+            *reinterpret_cast<uint4 *>(&Uh[r * US + 8 * c8]) = *reinterpret_cast<const uint4 *>(gh + g);
+            if (SPLIT_U)
+                *reinterpret_cast<uint4 *>(&Ul[r * US + 8 * c8]) = *reinterpret_cast<const uint4 *>(gl + g);
+        }
+        const int64_t p0 = posmod(dbase + kk, it.cap);
+        for (int e = tid; e < kCorrTQ + TK; e += 256) {
+            const float v = it.ring[p0 + e];
+            const T h = (T)v;
+            const T l = (T)(v - (float)h);
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int i = e - s;
+                if (i >= 0 && i < DL) {
+                    Dh[s * DL + i] = h;
+                    Dl[s * DL + i] = l;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 32) {
+            const int idx = wave * 16 + li + ks + 8 * lk;
+            const int sft = idx & 7;
+            const T8 bh = *reinterpret_cast<const T8 *>(&Dh[sft * DL + idx - sft]);
+            const T8 bl = *reinterpret_cast<const T8 *>(&Dl[sft * DL + idx - sft]);
+#pragma unroll
+            for (int m = 0; m < MBMAX; ++m) {
+                if (m < it.mb) {
+                    const int off = (m * 16 + li) * US + ks + 8 * lk;
+                    const T8 ah = *reinterpret_cast<const T8 *>(&Uh[off]);
+                    acc[m] = mfma16(ah, bl, acc[m]);
+                    if (SPLIT_U) acc[m] = mfma16(*reinterpret_cast<const T8 *>(&Ul[off]), bh, acc[m]);
+                    acc[m] = mfma16(ah, bh, acc[m]);
                 }
             }
         }
@@ -156,7 +274,21 @@ __global__ __launch_bounds__(256) void corr_f32_kernel(const CorrItem *__restric
     }
 }
 
-hipError_t launch_corr_reduced(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items);
+hipError_t launch_corr_reduced(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items) {
+    switch (precision) {
+        case LLOID_BF16X3:
+            hipLaunchKernelGGL((corr16_kernel<__bf16, bf16x8, true>), dim3(n_items), dim3(256), 0, ctx.stream, items,
+                               ctx.stride_ctr);
+            break;
+        case LLOID_FP16:
+            hipLaunchKernelGGL((corr16_kernel<_Float16, halfx8, false>), dim3(n_items), dim3(256), 0, ctx.stream,
+                               items, ctx.stride_ctr);
+            break;
+        default:
+            return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_corr(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items) {
     if (n_items == 0) return hipSuccess;
@@ -201,9 +333,19 @@ hipError_t launch_reduce(const LaunchCtx &ctx, const ReduceItem *items, int32_t 
 //       + sum over slices at rate j of W~^s (rows) x y^s (window)   [MFMA]
 // Level j >= 1 is kept in LDS for the next level; level 0 goes to the SNR
 // series (interleaved re, im) and to per-lane running peaks.  The W~ rows of
-// all slices of a level are staged together in LDS with row stride
-// SW = 2 mod 32 so the 16 rows x 2 taps of a half-wave hit distinct banks;
-// level buffers use row stride S = 8 mod 32.
+// all slices of a level are staged together in LDS (row stride SW chosen so
+// a half-wave's fragment reads hit distinct banks); level buffers use row
+// stride S = 2 mod 32.
+//
+// The polyphase upsample is a banded contraction into the same MFMA
+// accumulator: for the 16 output columns of a block starting at level index
+// i0, with q0 = floor(i0/p) and lane column c (i = i0 + c, q = floor(i/p),
+// ph = i mod p, off = q - q0),
+//   H_up(prev)[r][c] = sum_k prev[r][q0 - N_up + k] Ker[k][c],
+//   Ker[k][c] = z_ph[off + 2 N_up - k]  for off <= k <= off + 2 N_up, else 0,
+// and for phase 0 Ker is the unit vector at k = off + N_up (the copy case of
+// Eq. (upsample)).  off <= 7 and 2 N_up <= 16, so a 24- (FP32) or 32-wide
+// (16-bit) window of prev holds every tap.
 struct PeakCand {
     float p2;
     int idx;
@@ -214,17 +356,19 @@ __device__ __forceinline__ bool better(float p2, int idx, float bp2, int bidx) {
     return p2 > bp2 || (p2 == bp2 && idx < bidx);
 }
 
-__device__ __forceinline__ float upsample_at(const float *__restrict__ prev_row, int i, int lo_prev, int logp,
-                                             const float *__restrict__ taps, int ntap, int nup) {
-    const int q = i >> logp;
-    const int ph = i & ((1 << logp) - 1);
-    if (ph == 0) return prev_row[q - lo_prev];
-    const float *z = taps + ph * kUpTaps;
-    const float *src = prev_row + (q + nup - lo_prev);
-    float s = 0.0f;
-    for (int t = 0; t < ntap; ++t) s = fmaf(src[-t], z[t], s);
-    return s;
+__device__ __forceinline__ float ker_value(int k, int off, int ph, int nup, const float *__restrict__ taps) {
+    if (ph == 0) return k == off + nup ? 1.0f : 0.0f;
+    const int t = off + 2 * nup - k;
+    return (t >= 0 && t <= 2 * nup) ? taps[ph * kUpTaps + t] : 0.0f;
 }
+
+struct UpArgs {
+    const float *prev;       // level j+1 buffer, row stride S
+    int S, n_prev, m0;       // m0: buffer index of the window start
+    int off, ph, nup;
+    const float *taps;       // sub-kernels of this stage, [p][kUpTaps]
+    bool valid;
+};
 
 template <typename Op>
 __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ items, const MixBank *__restrict__ banks,
@@ -245,7 +389,6 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ it
     const int64_t k = *stride_ctr;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int li = lane & 15, lg = lane >> 4;
-    const int ntap = 2 * nup + 1;
 
     float *prev = bufA, *cur = bufB;
     int lo_prev = 0;
@@ -269,6 +412,7 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ it
         const bool has_up = (j < B.nlev - 1);
         const int logp = has_up ? __ffs(B.p[j + 1]) - 1 : 0;
         const float *taps = has_up ? uptaps + (B.p[j + 1] - 1) * kUpTaps : nullptr;
+        const int n_prev = has_up ? B.n[j + 1] : 0;
         const int nb = (n + 15) >> 4;
         for (int cb = wave; cb < nb; cb += 4) {
             const int c = cb * 16 + li;
@@ -282,17 +426,20 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ it
                 Op::contract(Y, ms, pos0, valid, Ws, SW, lb, li, lg, acc);
                 lb += ms.Lpad;
             }
+            if (has_up) {
+                const int i0 = lo + cb * 16;
+                const int q0 = i0 >> logp;   // arithmetic shift: floor for negative indices
+                const int i = i0 + li;
+                UpArgs ua{prev, S, n_prev, q0 - nup - lo_prev, (i >> logp) - q0, i & ((1 << logp) - 1), nup,
+                          taps, valid};
+                Op::upsample(ua, li, lg, acc);
+            }
             if (!valid) continue;
+            if (j > 0) {
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
+                for (int m = 0; m < 2; ++m)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = m * 16 + lg * 4 + v;
-                    float val = acc[m][v];
-                    if (has_up) val += upsample_at(prev + r * S, lo + c, lo_prev, logp, taps, ntap, nup);
-                    acc[m][v] = val;
-                    if (j > 0) cur[r * S + c] = val;
-                }
+                    for (int v = 0; v < 4; ++v) cur[(m * 16 + lg * 4 + v) * S + c] = acc[m][v];
             }
             if (j == 0) {
                 const int t = it.t0 + c;
@@ -357,34 +504,167 @@ struct MixF32 {
             Ws[r * SW + lbase + l] = ms.W[(int64_t)(r0 + r) * Lp + l];
         }
     }
+    // All basis-output loads of the column block are issued before the first
+    // MFMA, so their latency is paid once per block, not once per k-step.
     static __device__ __forceinline__ void contract(const float *Y, const MixSlice &ms, int64_t pos0, bool valid,
                                                     const float *Ws, int SW, int lb, int li, int lg,
                                                     floatx4 (&acc)[2]) {
+        constexpr int KS = kMaxBasis / 4;
         const int64_t rs = 2 * (int64_t)ms.capY;
-        for (int l = 0; l < ms.Lpad; l += 4) {
-            const float b = valid ? Y[(int64_t)(l + lg) * rs + pos0] : 0.0f;
-            const float a0 = Ws[li * SW + lb + l + lg];
-            const float a1 = Ws[(16 + li) * SW + lb + l + lg];
+        const int nks = ms.Lpad >> 2;
+        float bv[KS];
+#pragma unroll
+        for (int t = 0; t < KS; ++t) bv[t] = (valid && t < nks) ? Y[(int64_t)(4 * t + lg) * rs + pos0] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+            if (t < nks) {
+                const float a0 = Ws[li * SW + lb + 4 * t + lg];
+                const float a1 = Ws[(16 + li) * SW + lb + 4 * t + lg];
+                acc[0] = mfma_16x16x4_f32(a0, bv[t], acc[0]);
+                acc[1] = mfma_16x16x4_f32(a1, bv[t], acc[1]);
+            }
+        }
+    }
+    // 24-wide window, six K-steps of 4
+    static __device__ __forceinline__ void upsample(const UpArgs &u, int li, int lg, floatx4 (&acc)[2]) {
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const int kk = 4 * t + lg;
+            const float b = u.valid ? ker_value(kk, u.off, u.ph, u.nup, u.taps) : 0.0f;
+            const int idx = min(u.m0 + kk, u.n_prev - 1);
+            const float a0 = u.prev[li * u.S + idx];
+            const float a1 = u.prev[(16 + li) * u.S + idx];
             acc[0] = mfma_16x16x4_f32(a0, b, acc[0]);
             acc[1] = mfma_16x16x4_f32(a1, b, acc[1]);
         }
     }
 };
 
-hipError_t launch_mix_reduced(const LaunchCtx &ctx, int precision, const MixItem *items, int32_t n_items,
-                              const MixBank *banks, const MixSlice *slices, const float *uptaps, float *series,
-                              PartialPeak *partials, int32_t F, int32_t n_det, int32_t S, int32_t SW, int32_t nup);
+// 16-bit mixing on v_mfma_f32_16x16x32_{bf16,f16}.  The W~ rows are staged in
+// LDS as T (hi part, then lo part at offset 32 SW), row stride SW = 8 mod 64
+// elements so each 16-B fragment read of a half-wave hits distinct banks.  The
+// basis outputs are FP32 in the ring and are split on the fly:
+// y = y_hi + y_lo, y_hi = T(y), y_lo = T(y - y_hi).
+//   SPLIT_W (bf16x3): W_hi y_lo + W_lo y_hi + W_hi y_hi
+//   otherwise (fp16): W y_lo + W y_hi
+template <typename T, typename T8, bool SPLIT_W>
+struct Mix16 {
+    static __device__ __forceinline__ T8 mfma_in(const T *p) { return *reinterpret_cast<const T8 *>(p); }
+    static __device__ __forceinline__ void stage_w(const MixSlice &ms, int r0, float *Wsf, int SW, int lbase,
+                                                   int tid) {
+        T *wh = reinterpret_cast<T *>(Wsf);
+        T *wl = wh + kMixTM * SW;
+        const int Lp = ms.Lpad;
+        const T *gh = static_cast<const T *>(ms.Whi);
+        const T *gl = static_cast<const T *>(ms.Wlo);
+        for (int e = tid; e < kMixTM * Lp; e += 256) {
+            const int r = e / Lp, l = e % Lp;
+            wh[r * SW + lbase + l] = gh[(int64_t)(r0 + r) * Lp + l];
+            if (SPLIT_W) wl[r * SW + lbase + l] = gl[(int64_t)(r0 + r) * Lp + l];
+        }
+    }
+    static __device__ __forceinline__ void contract(const float *Y, const MixSlice &ms, int64_t pos0, bool valid,
+                                                    const float *Wsf, int SW, int lb, int li, int lg,
+                                                    floatx4 (&acc)[2]) {
+        constexpr int KS = kMaxBasis / 32;
+        const T *wh = reinterpret_cast<const T *>(Wsf);
+        const T *wl = wh + kMixTM * SW;
+        const int64_t rs = 2 * (int64_t)ms.capY;
+        const int nks = ms.Lpad >> 5;
+        float yv[KS][8];
+#pragma unroll
+        for (int t = 0; t < KS; ++t)
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                yv[t][j] = (valid && t < nks) ? Y[(int64_t)(32 * t + 8 * lg + j) * rs + pos0] : 0.0f;
+#pragma unroll
+        for (int t = 0; t < KS; ++t) {
+            if (t < nks) {
+                T8 bh, bl;
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const T h = (T)yv[t][j];
+                    bh[j] = h;
+                    bl[j] = (T)(yv[t][j] - (float)h);
+                }
+#pragma unroll
+                for (int m = 0; m < 2; ++m) {
+                    const int off = (m * 16 + li) * SW + lb + 32 * t + 8 * lg;
+                    const T8 ah = mfma_in(wh + off);
+                    acc[m] = mfma16(ah, bl, acc[m]);
+                    if (SPLIT_W) acc[m] = mfma16(mfma_in(wl + off), bh, acc[m]);
+                    acc[m] = mfma16(ah, bh, acc[m]);
+                }
+            }
+        }
+    }
+    // 32-wide window, one K-step; both operands split (three products), so
+    // the interpolation keeps ~16 (bf16) or ~22 (fp16) significant bits
+    static __device__ __forceinline__ void upsample(const UpArgs &u, int li, int lg, floatx4 (&acc)[2]) {
+        T8 kh, kl;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const float kv = u.valid ? ker_value(8 * lg + j, u.off, u.ph, u.nup, u.taps) : 0.0f;
+            const T h = (T)kv;
+            kh[j] = h;
+            kl[j] = (T)(kv - (float)h);
+        }
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            T8 ph, pl;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int idx = min(u.m0 + 8 * lg + j, u.n_prev - 1);
+                const float pv = u.prev[(m * 16 + li) * u.S + idx];
+                const T h = (T)pv;
+                ph[j] = h;
+                pl[j] = (T)(pv - (float)h);
+            }
+            acc[m] = mfma16(ph, kl, acc[m]);
+            acc[m] = mfma16(pl, kh, acc[m]);
+            acc[m] = mfma16(ph, kh, acc[m]);
+        }
+    }
+};
+
+// Raise the dynamic-LDS limit of the kernels whose tiles depend on the plan
+// (gfx950 has 160 KB of LDS per work group).
+hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(down_kernel),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)down_bytes);
+    if (e != hipSuccess) return e;
+    const void *mix = nullptr;
+    switch (precision) {
+        case LLOID_FP32: mix = reinterpret_cast<const void *>(mix_kernel<MixF32>); break;
+        case LLOID_BF16X3: mix = reinterpret_cast<const void *>(mix_kernel<Mix16<__bf16, bf16x8, true>>); break;
+        case LLOID_FP16: mix = reinterpret_cast<const void *>(mix_kernel<Mix16<_Float16, halfx8, false>>); break;
+        default: return hipErrorNotSupported;
+    }
+    return hipFuncSetAttribute(mix, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mix_bytes);
+}
 
 hipError_t launch_mix(const LaunchCtx &ctx, int precision, const MixItem *items, int32_t n_items,
                       const MixBank *banks, const MixSlice *slices, const float *uptaps, float *series,
                       PartialPeak *partials, int32_t F, int32_t n_det, int32_t S, int32_t SW, int32_t nup) {
     if (n_items == 0) return hipSuccess;
-    if (precision != LLOID_FP32)
-        return launch_mix_reduced(ctx, precision, items, n_items, banks, slices, uptaps, series, partials, F,
-                                  n_det, S, SW, nup);
     const size_t lds = (size_t)(2 * kMixTM * S + kMixTM * SW) * sizeof(float);
-    hipLaunchKernelGGL(mix_kernel<MixF32>, dim3(n_items), dim3(256), lds, ctx.stream, items, banks, slices, uptaps,
-                       series, partials, F, n_det, S, SW, nup, ctx.stride_ctr);
+    switch (precision) {
+        case LLOID_FP32:
+            hipLaunchKernelGGL(mix_kernel<MixF32>, dim3(n_items), dim3(256), lds, ctx.stream, items, banks, slices,
+                               uptaps, series, partials, F, n_det, S, SW, nup, ctx.stride_ctr);
+            break;
+        case LLOID_BF16X3:
+            hipLaunchKernelGGL((mix_kernel<Mix16<__bf16, bf16x8, true>>), dim3(n_items), dim3(256), lds, ctx.stream,
+                               items, banks, slices, uptaps, series, partials, F, n_det, S, SW, nup, ctx.stride_ctr);
+            break;
+        case LLOID_FP16:
+            hipLaunchKernelGGL((mix_kernel<Mix16<_Float16, halfx8, false>>), dim3(n_items), dim3(256), lds,
+                               ctx.stream, items, banks, slices, uptaps, series, partials, F, n_det, S, SW, nup,
+                               ctx.stride_ctr);
+            break;
+        default:
+            return hipErrorNotSupported;
+    }
     return hipGetLastError();
 }
 
@@ -438,9 +718,39 @@ hipError_t launch_normalize(hipStream_t st, const double *const *W64, const int3
     return hipGetLastError();
 }
 
+// v = src * row_scale -> hi = T(v) (round to nearest even), lo = T(v - hi)
+// with the residual formed in FP64 (lo is skipped when dst_lo is NULL).
+template <typename T>
+__global__ void convert_split_kernel(const double *__restrict__ src, int32_t rows, int32_t cols, int32_t src_ld,
+                                     const double *__restrict__ row_scale, T *__restrict__ hi, T *__restrict__ lo,
+                                     int32_t dst_ld) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)rows * cols) return;
+    const int r = (int)(e / cols), c = (int)(e % cols);
+    const double v = src[(int64_t)r * src_ld + c] * (row_scale ? row_scale[r] : 1.0);
+    const T h = (T)(float)v;
+    hi[(int64_t)r * dst_ld + c] = h;
+    if (lo) lo[(int64_t)r * dst_ld + c] = (T)(float)(v - (double)(float)h);
+}
+
 hipError_t launch_convert_reduced(hipStream_t st, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
                                   const double *row_scale, int precision, int role, void *dst_hi, void *dst_lo,
-                                  int32_t dst_ld, float *row_scale_out);
+                                  int32_t dst_ld, float *row_scale_out) {
+    (void)role;
+    (void)row_scale_out;
+    const int64_t n = (int64_t)rows * cols;
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (precision == LLOID_BF16X3) {
+        hipLaunchKernelGGL(convert_split_kernel<__bf16>, grid, dim3(256), 0, st, src, rows, cols, src_ld, row_scale,
+                           static_cast<__bf16 *>(dst_hi), static_cast<__bf16 *>(dst_lo), dst_ld);
+    } else if (precision == LLOID_FP16) {
+        hipLaunchKernelGGL(convert_split_kernel<_Float16>, grid, dim3(256), 0, st, src, rows, cols, src_ld,
+                           row_scale, static_cast<_Float16 *>(dst_hi), static_cast<_Float16 *>(dst_lo), dst_ld);
+    } else {
+        return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
 
 __global__ void convert_f32_kernel(const double *__restrict__ src, int32_t rows, int32_t cols, int32_t src_ld,
                                    const double *__restrict__ row_scale, float *__restrict__ dst, int32_t dst_ld) {

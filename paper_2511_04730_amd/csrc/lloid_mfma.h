@@ -27,5 +27,7 @@ __device__ __forceinline__ floatx4 mfma_16x16x32_bf16(bf16x8 a, bf16x8 b, floatx
 __device__ __forceinline__ floatx4 mfma_16x16x32_f16(halfx8 a, halfx8 b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ floatx4 mfma16(bf16x8 a, bf16x8 b, floatx4 c) { return mfma_16x16x32_bf16(a, b, c); }
+__device__ __forceinline__ floatx4 mfma16(halfx8 a, halfx8 b, floatx4 c) { return mfma_16x16x32_f16(a, b, c); }
 
 }  // namespace lloid

@@ -107,6 +107,16 @@ struct lloid_plan {
     float *d_uptaps = nullptr;
     int64_t *d_stride = nullptr;
     int64_t series_floats = 0, n_peaks = 0, total_templates = 0;
+
+    // graph mode (LLOID_OPT_GRAPH)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    float *d_instage = nullptr;   // [n_det][F] strain staging read by the graph
+    float *g_snr = nullptr;
+    lloid_peak *g_peaks = nullptr;
+    uint32_t g_gap = 0;
     double flops = 0.0;
 
     // per-kernel event timing (lloid_profile_*)
@@ -131,7 +141,19 @@ struct lloid_plan {
         *p = static_cast<T *>(q);
         return LLOID_OK;
     }
+    // free a plan-time staging buffer early
+    void release(void *p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) {
+            (void)hipFree(p);
+            allocs.erase(it);
+        }
+    }
     ~lloid_plan() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }
@@ -263,7 +285,8 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
             ps.N = S.n_taps;
             ps.L = S.n_basis;
             ps.Npad = (int)round_up(S.n_taps, kCorrTK);
-            ps.Lpad = (int)round_up(S.n_basis, 16);
+            // 16-bit MFMA takes 32 basis vectors per step in the mixing
+            ps.Lpad = (int)round_up(S.n_basis, P->precision == LLOID_FP32 ? 16 : 32);
             ps.la = pb.la[ps.level];
             ps.delay = S.delay;
             ps.nsplit = (int)((ps.Npad + kCorrSplitK - 1) / kCorrSplitK);
@@ -347,20 +370,43 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
             for (int s = 0; s < B.n_slices; ++s) {
                 const int id = sidx0 + s;
                 PSlice &ps = P->slices[id];
-                // mixing rows [rows_pad][Lpad]
-                ST_OK(P->alloc(&ps.W32, (size_t)pb.rows_pad * ps.Lpad));
-                HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, LLOID_FP32, ROLE_MIXING, ps.W32,
-                                           nullptr, nullptr, ps.Lpad, nullptr));
-                // basis [Lpad][Npad]
+                // mixing rows [rows_pad][Lpad], basis [Lpad][Npad], zero padded
                 HIP_OK(hipMemcpyAsync(u64, B.slices[s].basis, sizeof(double) * ps.L * ps.N, hipMemcpyHostToDevice,
                                       st));
-                ST_OK(P->alloc(&ps.U32, (size_t)ps.Lpad * ps.Npad));
-                HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, LLOID_FP32, ROLE_BASIS, ps.U32,
-                                           nullptr, nullptr, ps.Npad, nullptr));
+                if (P->precision == LLOID_FP32) {
+                    ST_OK(P->alloc(&ps.W32, (size_t)pb.rows_pad * ps.Lpad));
+                    HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, LLOID_FP32, ROLE_MIXING, ps.W32,
+                                               nullptr, nullptr, ps.Lpad, nullptr));
+                    ST_OK(P->alloc(&ps.U32, (size_t)ps.Lpad * ps.Npad));
+                    HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, LLOID_FP32, ROLE_BASIS, ps.U32,
+                                               nullptr, nullptr, ps.Npad, nullptr));
+                } else {
+                    // 16-bit parts: hi and lo of W (bf16x3) or W alone (fp16);
+                    // hi and lo of U (bf16x3) or U alone (fp16)
+                    const bool split = P->precision == LLOID_BF16X3;
+                    uint16_t *wh = nullptr, *wl = nullptr, *uh = nullptr, *ul = nullptr;
+                    ST_OK(P->alloc(&wh, (size_t)pb.rows_pad * ps.Lpad));
+                    if (split) ST_OK(P->alloc(&wl, (size_t)pb.rows_pad * ps.Lpad));
+                    ST_OK(P->alloc(&uh, (size_t)ps.Lpad * ps.Npad));
+                    if (split) ST_OK(P->alloc(&ul, (size_t)ps.Lpad * ps.Npad));
+                    HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, P->precision, ROLE_MIXING, nullptr,
+                                               wh, wl, ps.Lpad, nullptr));
+                    HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, P->precision, ROLE_BASIS, nullptr,
+                                               uh, ul, ps.Npad, nullptr));
+                    ps.Whi = wh;
+                    ps.Wlo = wl;
+                    ps.Uhi = uh;
+                    ps.Ulo = ul;
+                }
                 HIP_OK(hipStreamSynchronize(st));   // u64 staging is reused
             }
+            for (int s = 0; s < B.n_slices; ++s) P->release(w64[sidx0 + s]);
+            P->release(d_wp);
+            P->release(d_Ls);
+            P->release(inv);
         }
         HIP_OK(hipStreamSynchronize(st));
+        P->release(u64);
     }
 
     // ---------------------------------------------------------- per-slice buffers
@@ -420,7 +466,7 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                     items.push_back(DownItem{xr.base + det * xr.det_stride, dr.base + det * dr.det_stride, dtaps[D],
                                              D, c, f, m0, std::min(chunk, f - m0), xr.cap, dr.cap, ndown});
         }
-        if (lds * 4 > 64 * 1024) return LLOID_E_UNSUPPORTED;
+        if (lds * 4 > kMaxLdsBytes) return LLOID_E_UNSUPPORTED;
         P->down_lds = lds;
         P->n_downitems = (int)items.size();
         ST_OK(upload(P, &P->d_down, items, st));
@@ -528,9 +574,13 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         }
         for (auto &kv : P->rings)
             if (kv.first > 1) P->flops += (double)ND * (F / kv.first) * 2.0 * (2 * kv.first * ndown + 1);
-        P->mixS = (int)round_up(std::max(S, 1), 32) + 8;    // 8 mod 32
-        P->mixSW = (int)round_up(std::max(SW, 16), 32) + 2;  // 2 mod 32
-        if ((2 * kMixTM * P->mixS + kMixTM * P->mixSW) * 4 > 64 * 1024) return LLOID_E_UNSUPPORTED;
+        P->mixS = (int)round_up(std::max(S, 1), 32) + 2;    // 2 mod 32
+        // W staging row stride: FP32 words 2 mod 32; 16-bit elements 8 mod 64
+        P->mixSW = P->precision == LLOID_FP32 ? (int)round_up(std::max(SW, 16), 32) + 2
+                                              : (int)round_up(std::max(SW, 32), 32) + 8;
+        const size_t mix_lds = (size_t)(2 * kMixTM * P->mixS + kMixTM * P->mixSW) * 4;
+        if (mix_lds > (size_t)kMaxLdsBytes) return LLOID_E_UNSUPPORTED;
+        HIP_OK(configure_lds(P->precision, mix_lds, (size_t)P->down_lds * 4));
         P->n_mix = (int)items.size();
         P->n_peakitems = (int)pk.size();
         ST_OK(upload(P, &P->d_mbanks, mb, st));
@@ -540,6 +590,7 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         ST_OK(P->alloc(&P->d_partials, (size_t)std::max<int64_t>(part_off, 1)));
     }
     ST_OK(P->alloc(&P->d_stride, 1));
+    ST_OK(P->alloc(&P->d_instage, (size_t)ND * F));
     HIP_OK(hipStreamSynchronize(st));
     guard.p = nullptr;
     *out = P;
@@ -580,10 +631,57 @@ lloid_status lloid_plan_query(const lloid_plan *P, int32_t what, int32_t index, 
     }
 }
 
+static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *strain, uint32_t gap_mask,
+                                   float *snr, lloid_peak *peaks);
+
 lloid_status lloid_push_stride(lloid_plan *P, const float *strain, uint32_t gap_mask, float *snr, lloid_peak *peaks,
                                void *stream) {
     if (!P || !strain || !peaks) return LLOID_E_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!P->use_graph || P->profiling) {
+        ST_OK(enqueue_stride(P, st, strain, gap_mask, snr, peaks));
+        P->stride += 1;
+        return LLOID_OK;
+    }
+    if (!P->gexec || P->g_snr != snr || P->g_peaks != peaks || P->g_gap != gap_mask) {
+        if (P->gexec) HIP_OK(hipGraphExecDestroy(P->gexec));
+        if (P->graph) HIP_OK(hipGraphDestroy(P->graph));
+        P->gexec = nullptr;
+        P->graph = nullptr;
+        HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+        const lloid_status s = enqueue_stride(P, P->cap_stream, P->d_instage, gap_mask, snr, peaks);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(P->cap_stream, &g);
+        if (s != LLOID_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return LLOID_E_HIP;
+        P->graph = g;
+        HIP_OK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+        P->g_snr = snr;
+        P->g_peaks = peaks;
+        P->g_gap = gap_mask;
+    }
+    HIP_OK(hipMemcpyAsync(P->d_instage, strain, sizeof(float) * P->n_det * P->F, hipMemcpyDeviceToDevice, st));
+    HIP_OK(hipGraphLaunch(P->gexec, st));
+    P->stride += 1;
+    return LLOID_OK;
+}
+
+lloid_status lloid_set_option(lloid_plan *P, int32_t option, int64_t value) {
+    if (!P) return LLOID_E_ARG;
+    if (option == LLOID_OPT_GRAPH) {
+        if (value != 0 && value != 1) return LLOID_E_ARG;
+        if (value && !P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+        P->use_graph = value != 0;
+        return LLOID_OK;
+    }
+    return LLOID_E_ARG;
+}
+
+static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *strain, uint32_t gap_mask,
+                                   float *snr, lloid_peak *peaks) {
     LaunchCtx ctx{st, P->d_stride};
     const Ring &xr = P->rings[1];
     HIP_OK(P->mark(LLOID_K_INGEST, st, true));
@@ -606,7 +704,6 @@ lloid_status lloid_push_stride(lloid_plan *P, const float *strain, uint32_t gap_
     HIP_OK(launch_peaks(ctx, P->d_peakitems, P->n_peakitems, P->d_partials, peaks, P->cfg.snr_threshold,
                         P->d_stride));
     HIP_OK(P->mark(LLOID_K_PEAKS, st, false));
-    P->stride += 1;
     return LLOID_OK;
 }
 

@@ -73,6 +73,10 @@ class LloidPlan:
         self.bank_peak_offset = [self.query(L.Q_BANK_PEAK_OFFSET, b) for b in range(self.n_banks)]
         self.flops_per_stride = self.query(L.Q_FLOPS_PER_STRIDE)
 
+    def set_graph(self, enable: bool = True) -> None:
+        """Replay one captured HIP graph per stride (LLOID_OPT_GRAPH)."""
+        L.check(self.lib.lloid_set_option(self.handle, 0, 1 if enable else 0), "lloid_set_option")
+
     def query(self, what: int, index: int = 0) -> int:
         v = ctypes.c_int64()
         L.check(self.lib.lloid_plan_query(self.handle, what, index, ctypes.byref(v)), "lloid_plan_query")

@@ -1,0 +1,54 @@
+"""Reduced-precision forms (BF16x3, FP16 with split strain and basis
+outputs) against the FP64 oracle: SNR error within 1e-3 (relative above the
+trigger threshold, absolute / 4 below), triggers consistent."""
+import numpy as np
+import pytest
+
+import synth
+
+from lloid_check import check_peaks, run_gpu, run_oracle, snr_error
+from test_gpu_parity import _ragged_banks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GATE = 1e-3
+EXPECT = {"bf16x3": 1e-4, "fp16": 1e-3}
+
+
+@pytest.fixture(scope="module")
+def plan_cls():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_04730_amd import LloidPlan
+    return LloidPlan
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16"])
+def test_ragged_banks_reduced_precision(plan_cls, precision):
+    banks = _ragged_banks()
+    F = 4096
+    x = synth.gaussian_strain(81, 2, 5 * F)
+    plan = plan_cls(banks, F, 2, precision)
+    z, pk = run_gpu(plan, x, 0, 5)
+    for b, bank in enumerate(banks):
+        ref = run_oracle(bank, x, F, 0, 5)
+        eps = snr_error(z[b], ref)
+        print(f"{precision} bank {b} eps={eps:.3e}")
+        assert eps <= min(GATE, EXPECT[precision])
+        check_peaks(pk[b], ref, F, float(np.abs(z[b] - ref).max()))
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16"])
+def test_realistic_bank_reduced_precision(plan_cls, precision):
+    c2 = synth.cached_workload("c2", synth.config2)
+    F = c2.sample_rate
+    x = synth.workload_strain(c2, 66)
+    plan = plan_cls(c2.banks, F, 1, precision)
+    z, pk = run_gpu(plan, x, 65, 1)
+    ref = run_oracle(c2.banks[0], x, F, 65, 1)
+    eps = snr_error(z[0], ref)
+    rms = float(np.sqrt(np.mean(np.abs(z[0] - ref) ** 2) / np.mean(np.abs(ref) ** 2)))
+    print(f"realistic bank {precision}: eps={eps:.3e} rel_rms={rms:.3e}")
+    assert eps <= min(GATE, EXPECT[precision])
+    check_peaks(pk[0], ref, F, float(np.abs(z[0] - ref).max()))
