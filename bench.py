@@ -186,7 +186,7 @@ def main() -> int:
     samples = w.n_templates * F * ND * steps
     value = samples / (ms / 1e3)
     # per-kernel HIP-event timing over a second timed region (direct launches)
-    _, ms_p, prof = timed(plan, strides, 0, min(steps, 16), write, True)
+    _, prof = timed(plan, strides, 0, min(steps, 16), write, True)
     dom = max(("corr", "mix"), key=lambda k: prof[k][0])
     avg_ms = prof[dom][0] / max(prof[dom][1], 1)
     achieved = kf[dom] / (avg_ms / 1e3) / 1e12

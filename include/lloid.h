@@ -184,6 +184,45 @@ typedef enum { LLOID_INSPECT_DOWNSAMPLED = 0, LLOID_INSPECT_BASIS_OUT = 1 } lloi
 lloid_status lloid_inspect(lloid_plan *plan, int32_t what, int32_t index, int32_t det,
                            int64_t m_lo, int64_t m_hi, float *dst, void *stream);
 
+/* Gradient of the SNR-reconstruction loss, for refining compressed banks
+ * (an extension; the paper builds banks by SVD only, Sec. II.C.1):
+ *   L = sum over detectors, banks, real rows r and top-rate samples
+ *       t in [0, n_strides F) of (rho[r,t] - target[r,t])^2
+ * where rho is the plan's own output for the strain segment, filtered from
+ * zero history (the streaming state is reset first and left after stride
+ * n_strides).  rho is linear in every W^s and every U^s:
+ *   dL/dW^s = 2 G^s Y^s^T,  dL/dU^s[l,n] = 2 sum_q (W^s^T G^s)[l,q] d^s[q - delay - (N-1) + n],
+ * with Y^s the basis outputs, d^s the decimated strain and G^s the residual
+ * taken down to the slice's rate by the transposed upsampling stages.
+ *   strain_dev  device [n_det][n_strides F] float32
+ *   target_dev  device [n_strides][series floats] float32: per stride the
+ *               layout lloid_push_stride writes (e.g. the output of a plan
+ *               holding the uncompressed slices)
+ *   loss_out    host, receives L
+ *   dW_dev      device float32: for every slice in bank order, its
+ *               [2M_b][L_s] block, packed back to back
+ *   dU_dev      device float32: for every slice, its [L_s][N_s] block
+ * The gradient is with respect to the mixing rows the plan uses (create the
+ * plan with normalize = 0 to differentiate the given W).  The plan keeps a
+ * workspace of about twice the segment's series size (FP32 plans only:
+ * LLOID_E_UNSUPPORTED otherwise).  Synchronises `stream`. */
+lloid_status lloid_grad(lloid_plan *plan, const float *strain_dev, int32_t n_strides, const float *target_dev,
+                        double *loss_out, float *dW_dev, float *dU_dev, void *stream);
+
+/* Replace one slice's basis and mixing matrix (global slice index, banks in
+ * order) with device float64 arrays U [L][N] and W [2M][L]; they are
+ * converted to the plan's precision.  Plans created with normalize = 1 return
+ * LLOID_E_STATE (the row norms couple all slices of a bank). */
+lloid_status lloid_set_slice(lloid_plan *plan, int32_t slice, const double *U_dev, const double *W_dev,
+                             void *stream);
+
+/* Re-orthonormalise refined bases in float64 on the device (CholeskyQR2):
+ * two passes of G = U U^T = C C^T (Cholesky), U <- C^-1 U, W <- W C, so
+ * that U has orthonormal rows and W U is unchanged.  U_dev [L][N], W_dev
+ * [rows][L], device float64, updated in place; 1 <= L <= 160.
+ * LLOID_E_STATE if a Gram matrix is not positive definite.  Synchronises. */
+lloid_status lloid_orthonormalize(double *U_dev, int32_t L, int32_t N, double *W_dev, int32_t rows, void *stream);
+
 /* Plan options (lloid_set_option).
  *   LLOID_OPT_GRAPH  1: lloid_push_stride copies the strain into a
  *                    plan-owned staging buffer on the call's stream and then

@@ -357,3 +357,104 @@ def concatenated_filters(bank, top_rate: int, mixing: Optional[List[np.ndarray]]
         R = W @ np.asarray(s.basis, np.float64)        # [2M, N], chronological taps
         out[:, s.delay:s.delay + s.n_taps] += R[:, ::-1]   # tau index j = delay + N-1-m
     return out
+
+
+# ---------------------------------------------------------------------------
+# Gradient of the SNR-reconstruction loss (bank refinement; not in the paper)
+# ---------------------------------------------------------------------------
+
+def upsample_adjoint(g: np.ndarray, g_lo: int, p: int, a_lo: int, a_hi: int, n_up: int = N_UP) -> np.ndarray:
+    """Transpose of `upsample`: the forward adds a[floor(i/p) + N_up - k] z_{i mod p}[k]
+    to output i (phase-0 outputs copy a[i/p]); the transpose adds g[i] times the
+    same weight to position floor(i/p) + N_up - k.  g covers level indices
+    g_lo .. g_lo + n - 1; returns the lower-rate array over [a_lo, a_hi)."""
+    z = polyphase_subkernels(p, n_up)
+    i = np.arange(g_lo, g_lo + g.shape[1])
+    q, ph = i // p, i % p
+    out = np.zeros((g.shape[0], a_hi - a_lo))
+    for k in range(2 * n_up + 1):
+        w = z[ph, k].copy()
+        w[ph == 0] = 1.0 if k == n_up else 0.0
+        dst = q + n_up - k - a_lo
+        assert dst.min() >= 0 and dst.max() < out.shape[1]
+        np.add.at(out.T, dst, (g * w[None, :]).T)
+    return out
+
+
+def _upsample_to_top(a: np.ndarray, chain, ranges, j: int, n_up: int) -> np.ndarray:
+    """Apply the upsampling stages from level j to the top level."""
+    for i in range(j, 0, -1):
+        a = upsample(a, ranges[i][0], chain[i - 1] // chain[i], ranges[i - 1][0], ranges[i - 1][1], n_up)
+    return a
+
+
+def _adjoint_to_level(g: np.ndarray, chain, ranges, j: int, n_up: int) -> np.ndarray:
+    """Apply the transposed upsampling stages from the top level down to level j."""
+    for i in range(1, j + 1):
+        g = upsample_adjoint(g, ranges[i - 1][0], chain[i - 1] // chain[i], ranges[i][0], ranges[i][1], n_up)
+    return g
+
+
+def loss_and_grad(x: np.ndarray, bank, target: np.ndarray, cfg: OracleConfig, t_lo: int, t_hi: int):
+    """L = sum_{r, t in [t_lo, t_hi)} (rho[r,t] - target[r,t])^2, rho the LLOID
+    output of the bank's own W and U (no row normalisation), and its gradient:
+
+      dL/dW^s[r,l] = 2 sum_t R[r,t] (Up_s y^s_l)[t]
+      dL/dU^s[l,n] = 2 sum_q (Up_s^T W^s^T R)[l,q] d^s[q - delay - (N-1) + n]
+
+    with R = rho - target and Up_s the upsampling stages from the slice's
+    rate to the top rate (rho is linear in W^s and in U^s).
+    Returns (L, [dW^s], [dU^s])."""
+    F = cfg.sample_rate
+    chain = rate_chain(bank, F)
+    ranges = level_ranges(chain, t_lo, t_hi, cfg.n_up)
+    mixing = [np.asarray(s.mixing, np.float64) for s in bank.slices]
+    rho = snr_series(x, bank, cfg, t_lo, t_hi, mixing=mixing)
+    R = rho - target
+    L = float(np.sum(R * R))
+    dW, dU = [], []
+    for s, W in zip(bank.slices, mixing):
+        j = chain.index(int(s.rate))
+        lo, hi = ranges[j]
+        D = F // s.rate
+        N = s.n_taps
+        d_lo = lo - s.delay - (N - 1)
+        d = downsample(x, D, d_lo, hi - s.delay, cfg.n_down)
+        y = correlate(np.asarray(s.basis, np.float64), d, d_lo, s.delay, lo, hi)
+        yhat = _upsample_to_top(y, chain, ranges, j, cfg.n_up)
+        dW.append(2.0 * R @ yhat.T)
+        g = _adjoint_to_level(R, chain, ranges, j, cfg.n_up)
+        dy = 2.0 * W.T @ g
+        H = sliding_window_view(d, N)          # H[i, n] = d[lo + i - delay - N + 1 + n]
+        dU.append(dy @ H)
+    return L, dW, dU
+
+
+def loss_only(x: np.ndarray, bank, target: np.ndarray, cfg: OracleConfig, t_lo: int, t_hi: int) -> float:
+    mixing = [np.asarray(s.mixing, np.float64) for s in bank.slices]
+    R = snr_series(x, bank, cfg, t_lo, t_hi, mixing=mixing) - target
+    return float(np.sum(R * R))
+
+
+def direct_bank(bank):
+    """The multirate-direct bank: every slice at full rank (U^s = H^s,
+    W^s = I), from the uncompressed slice templates."""
+    from types import SimpleNamespace
+    sl = [SimpleNamespace(rate=s.rate, delay=s.delay, basis=H, mixing=np.eye(H.shape[0]), n_taps=H.shape[1],
+                          n_basis=H.shape[0]) for s, H in zip(bank.slices, bank.templates)]
+    return SimpleNamespace(n_templates=bank.n_templates, slices=sl)
+
+
+# ---------------------------------------------------------------------------
+# Re-orthonormalisation of refined bases (CholeskyQR2, float64)
+# ---------------------------------------------------------------------------
+
+def cholesky_qr2(U: np.ndarray, W: np.ndarray):
+    """U^T = Q R with Q orthonormal columns, by two CholeskyQR passes:
+    G = U U^T = R^T R, U <- R^-T U, W <- W R^T.  W U is unchanged."""
+    for _ in range(2):
+        G = U @ U.T
+        C = np.linalg.cholesky(G)          # G = C C^T, C = R^T lower triangular
+        U = np.linalg.solve(C, U)          # R^-T U
+        W = W @ C                          # W R^T
+    return U, W

@@ -78,6 +78,12 @@ def load() -> ctypes.CDLL:
     lib.lloid_profile_enable.argtypes = [P, ctypes.c_int32]
     lib.lloid_profile_read.argtypes = [P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_int64)]
+    lib.lloid_grad.argtypes = [P, P, ctypes.c_int32, P, ctypes.POINTER(ctypes.c_double), P, P, P]
+    lib.lloid_grad.restype = ctypes.c_int
+    lib.lloid_set_slice.argtypes = [P, ctypes.c_int32, P, P, P]
+    lib.lloid_set_slice.restype = ctypes.c_int
+    lib.lloid_orthonormalize.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P]
+    lib.lloid_orthonormalize.restype = ctypes.c_int
     lib.lloid_set_option.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
     lib.lloid_set_option.restype = ctypes.c_int
     lib.lloid_status_string.argtypes = [ctypes.c_int]

@@ -104,8 +104,8 @@ struct LaunchCtx {
     const int64_t *stride_ctr;   // device stride counter
 };
 
-hipError_t launch_ingest(const LaunchCtx &, const float *strain, uint32_t gap_mask, float *xring,
-                         int64_t ring_det_stride, int32_t cap, int32_t F, int32_t n_det);
+hipError_t launch_ingest(const LaunchCtx &, const float *strain, int64_t src_det_stride, uint32_t gap_mask,
+                         float *xring, int64_t ring_det_stride, int32_t cap, int32_t F, int32_t n_det);
 hipError_t launch_down(const LaunchCtx &, const DownItem *items, int32_t n_items, int32_t max_lds_floats);
 hipError_t launch_corr(const LaunchCtx &, int precision, const CorrItem *items, int32_t n_items);
 hipError_t launch_reduce(const LaunchCtx &, const ReduceItem *items, int32_t n_items, int32_t max_rows);
@@ -117,6 +117,24 @@ hipError_t launch_peaks(const LaunchCtx &, const PeakItem *items, int32_t n_item
                         const PartialPeak *partials, lloid_peak *peaks, float threshold,
                         int64_t *stride_ctr_advance);
 hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes);
+
+// gradient and re-orthonormalisation (lloid_grad.hip)
+hipError_t launch_copy_window(hipStream_t, const float *ring, int64_t ring_ld, int32_t cap, int64_t a,
+                              int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off);
+hipError_t launch_residual(hipStream_t, const float *series, const float *target, int32_t M, int32_t F,
+                           float *R, int64_t ld, int64_t t0, double *loss_part, int32_t blocks);
+hipError_t launch_sum_f64(hipStream_t, const double *part, int32_t n, double *out);
+hipError_t launch_upsample_adjoint(hipStream_t, const float *g, int64_t g_ld, int64_t g_lo, int64_t ng,
+                                   float *out, int64_t o_ld, int64_t a_lo, int64_t na, int32_t rows,
+                                   int32_t p, int32_t nup, const float *taps);
+hipError_t launch_gemm_f32(hipStream_t, const float *A, int64_t sam, int64_t sak, const float *B,
+                           int64_t sbk, int64_t sbn, int64_t M, int64_t N, int64_t K, int64_t ksplit,
+                           float *part);
+hipError_t launch_sum_parts(hipStream_t, const float *part, int32_t nsplit, int64_t plane, int32_t rows,
+                            int32_t cols, int64_t p_ld, float *dst, int64_t d_ld, float alpha,
+                            int32_t accumulate);
+hipError_t launch_cholesky_qr2(hipStream_t, double *U, int32_t L, int32_t N, double *W, int32_t rows,
+                               double *G, int32_t *info);
 hipError_t launch_normalize(hipStream_t, const double *const *W64, const int32_t *Ls,
                             int32_t n_slices, int32_t rows, int32_t normalize, double *inv_norm);
 hipError_t launch_convert_rows(hipStream_t, const double *src, int32_t rows, int32_t cols,

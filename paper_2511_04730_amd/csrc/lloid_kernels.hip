@@ -28,24 +28,25 @@ __device__ __forceinline__ int64_t posmod(int64_t a, int64_t m) {
 }
 
 // ------------------------------------------------------------------ ingest
-__global__ void ingest_kernel(const float *__restrict__ strain, uint32_t gap_mask, float *__restrict__ xring,
-                              int64_t det_stride, int32_t cap, int32_t F, const int64_t *__restrict__ stride_ctr) {
+__global__ void ingest_kernel(const float *__restrict__ strain, int64_t src_det_stride, uint32_t gap_mask,
+                              float *__restrict__ xring, int64_t det_stride, int32_t cap, int32_t F,
+                              const int64_t *__restrict__ stride_ctr) {
     const int det = blockIdx.y;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= F) return;
     const int64_t k = *stride_ctr;
-    const float v = ((gap_mask >> det) & 1u) ? 0.0f : strain[(int64_t)det * F + i];
+    const float v = ((gap_mask >> det) & 1u) ? 0.0f : strain[(int64_t)det * src_det_stride + i];
     const int64_t pos = posmod(k * F + i, cap);
     float *r = xring + det * det_stride;
     r[pos] = v;
     r[pos + cap] = v;
 }
 
-hipError_t launch_ingest(const LaunchCtx &ctx, const float *strain, uint32_t gap_mask, float *xring,
-                         int64_t ring_det_stride, int32_t cap, int32_t F, int32_t n_det) {
+hipError_t launch_ingest(const LaunchCtx &ctx, const float *strain, int64_t src_det_stride, uint32_t gap_mask,
+                         float *xring, int64_t ring_det_stride, int32_t cap, int32_t F, int32_t n_det) {
     dim3 grid((F + 255) / 256, n_det);
-    hipLaunchKernelGGL(ingest_kernel, grid, dim3(256), 0, ctx.stream, strain, gap_mask, xring, ring_det_stride,
-                       cap, F, ctx.stride_ctr);
+    hipLaunchKernelGGL(ingest_kernel, grid, dim3(256), 0, ctx.stream, strain, src_det_stride, gap_mask, xring,
+                       ring_det_stride, cap, F, ctx.stride_ctr);
     return hipGetLastError();
 }
 

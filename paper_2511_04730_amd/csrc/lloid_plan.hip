@@ -632,7 +632,7 @@ lloid_status lloid_plan_query(const lloid_plan *P, int32_t what, int32_t index, 
 }
 
 static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *strain, uint32_t gap_mask,
-                                   float *snr, lloid_peak *peaks);
+                                   float *snr, lloid_peak *peaks, int64_t src_det_stride = 0);
 
 lloid_status lloid_push_stride(lloid_plan *P, const float *strain, uint32_t gap_mask, float *snr, lloid_peak *peaks,
                                void *stream) {
@@ -681,11 +681,12 @@ lloid_status lloid_set_option(lloid_plan *P, int32_t option, int64_t value) {
 }
 
 static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *strain, uint32_t gap_mask,
-                                   float *snr, lloid_peak *peaks) {
+                                   float *snr, lloid_peak *peaks, int64_t src_det_stride) {
     LaunchCtx ctx{st, P->d_stride};
     const Ring &xr = P->rings[1];
     HIP_OK(P->mark(LLOID_K_INGEST, st, true));
-    HIP_OK(launch_ingest(ctx, strain, gap_mask, xr.base, xr.det_stride, xr.cap, P->F, P->n_det));
+    HIP_OK(launch_ingest(ctx, strain, src_det_stride ? src_det_stride : P->F, gap_mask, xr.base, xr.det_stride,
+                         xr.cap, P->F, P->n_det));
     HIP_OK(P->mark(LLOID_K_INGEST, st, false));
     HIP_OK(P->mark(LLOID_K_DOWN, st, true));
     HIP_OK(launch_down(ctx, P->d_down, P->n_downitems, P->down_lds));
@@ -857,6 +858,265 @@ lloid_status lloid_inspect(lloid_plan *P, int32_t what, int32_t index, int32_t d
         return LLOID_OK;
     }
     return LLOID_E_ARG;
+}
+
+// ------------------------------------------------------------------ gradient
+// Forward over the segment with the stride kernels, capturing each stride's
+// new basis-output columns and decimated samples and the residual; then per
+// bank and detector the transposed upsampling chain and, per slice, the
+// three contractions of dL/dW, dL/dY and dL/dU (the last one on the
+// correlation kernel: a Hankel window of the decimated strain again).
+namespace {
+constexpr int64_t kGradSplitW = 16384;   // K split of dW = 2 G Y^T (K = time)
+constexpr int64_t kGradSplitU = 8192;    // K split of dU (K = time)
+constexpr int kLossBlocks = 64;
+
+int64_t seg_lo(const PBank &b, int j, int nup) {
+    int64_t lo = 0;
+    for (int i = 1; i <= j; ++i) lo = floordiv(lo, b.rates[i - 1] / b.rates[i]) - nup;
+    return lo;
+}
+int64_t seg_hi(const PBank &b, int j, int nup, int64_t top) {
+    int64_t hi = top;
+    for (int i = 1; i <= j; ++i) hi = floordiv(hi - 1, b.rates[i - 1] / b.rates[i]) + nup + 1;
+    return hi;
+}
+}  // namespace
+
+lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const float *target, double *loss_out,
+                        float *dW, float *dU, void *stream) {
+    if (!P || !strain || !target || !loss_out || !dW || !dU || T < 1) return LLOID_E_ARG;
+    if (P->precision != LLOID_FP32) return LLOID_E_UNSUPPORTED;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int F = P->F, ND = P->n_det, nup = P->nup;
+    const int64_t TF = (int64_t)T * F;
+    std::vector<void *> tmp;   // per-call buffers, freed on return
+    struct Free {
+        lloid_plan *P;
+        std::vector<void *> *v;
+        ~Free() {
+            (void)hipDeviceSynchronize();
+            for (void *p : *v) P->release(p);
+        }
+    } guard{P, &tmp};
+    auto get = [&](auto **p, size_t n, bool zero) -> lloid_status {
+        ST_OK(P->alloc(p, n, zero));
+        tmp.push_back(*p);
+        return LLOID_OK;
+    };
+    ST_OK(lloid_reset(P, stream));
+    const bool graph = P->use_graph;
+    P->use_graph = false;
+
+    // ---- workspace
+    float *series = nullptr;
+    lloid_peak *peaks = nullptr;
+    ST_OK(get(&series, (size_t)P->series_floats, false));
+    ST_OK(get(&peaks, (size_t)P->n_peaks, false));
+    const int nbd = (int)P->banks.size() * ND;
+    double *loss_part = nullptr, *loss_d = nullptr;
+    ST_OK(get(&loss_part, (size_t)T * nbd * kLossBlocks, true));
+    ST_OK(get(&loss_d, 1, true));
+    int64_t *zero = nullptr;
+    ST_OK(get(&zero, 1, true));
+    std::vector<float *> R(nbd, nullptr);
+    for (size_t b = 0; b < P->banks.size(); ++b)
+        for (int d = 0; d < ND; ++d) ST_OK(get(&R[b * ND + d], (size_t)2 * P->banks[b].M * TF, false));
+    const int ns = (int)P->slices.size();
+    std::vector<float *> yseg(ns, nullptr);
+    std::vector<int64_t> qld(ns), slo(ns), sq(ns);
+    std::map<int, int64_t> dlo;
+    for (int i = 0; i < ns; ++i) {
+        const PSlice &s = P->slices[i];
+        const PBank &b = P->banks[s.bank];
+        slo[i] = seg_lo(b, s.level, nup);
+        sq[i] = seg_hi(b, s.level, nup, TF) - slo[i];
+        qld[i] = round_up(sq[i], 64);
+        ST_OK(get(&yseg[i], (size_t)ND * s.Lpad * qld[i], true));
+        const int64_t need = slo[i] - s.delay - (s.N - 1);
+        dlo[s.D] = std::min(dlo.count(s.D) ? dlo[s.D] : 0, need);
+    }
+    std::map<int, float *> dseg;
+    std::map<int, int64_t> dlen;
+    for (auto &kv : dlo) {
+        const int D = kv.first;
+        dlen[D] = TF / D - kv.second + 256;
+        ST_OK(get(&dseg[D], (size_t)ND * (dlen[D] + 128), true));
+    }
+
+    // ---- forward with capture
+    for (int k = 0; k < T; ++k) {
+        ST_OK(enqueue_stride(P, st, strain + (int64_t)k * F, 0, series, peaks, TF));
+        for (size_t b = 0; b < P->banks.size(); ++b) {
+            const PBank &pb = P->banks[b];
+            for (int d = 0; d < ND; ++d) {
+                const int64_t so = pb.series_off + (int64_t)d * pb.M * F * 2;
+                HIP_OK(launch_residual(st, series + so, target + (int64_t)k * P->series_floats + so, pb.M, F,
+                                       R[b * ND + d], TF, (int64_t)k * F,
+                                       loss_part + ((int64_t)k * nbd + b * ND + d) * kLossBlocks, kLossBlocks));
+            }
+        }
+        for (int i = 0; i < ns; ++i) {
+            const PSlice &s = P->slices[i];
+            const int64_t a = (int64_t)k * s.rate + s.la;
+            for (int d = 0; d < ND; ++d)
+                HIP_OK(launch_copy_window(st, s.yring + d * s.ydet, 2LL * s.capY, s.capY, a, s.rate, s.L,
+                                          yseg[i] + (int64_t)d * s.Lpad * qld[i], qld[i], a - slo[i]));
+        }
+        for (auto &kv : dseg) {
+            const int D = kv.first;
+            const Ring &r = P->rings[D];
+            const int f = F / D;
+            const int64_t a = D == 1 ? (int64_t)k * F : (int64_t)k * f - P->ndown;
+            for (int d = 0; d < ND; ++d)
+                HIP_OK(launch_copy_window(st, r.base + d * r.det_stride, 0, r.cap, a, f, 1,
+                                          kv.second + d * (dlen[D] + 128), 0, a - dlo[D]));
+        }
+    }
+    P->stride = T;
+    P->use_graph = graph;
+    HIP_OK(launch_sum_f64(st, loss_part, T * nbd * kLossBlocks, loss_d));
+
+    // ---- transposed chain and contractions
+    int64_t gmax = 0, pmax = 0, dymax = 0;
+    for (int i = 0; i < ns; ++i) {
+        const PSlice &s = P->slices[i];
+        const int64_t rows = 2LL * P->banks[s.bank].M;
+        pmax = std::max(pmax, ((sq[i] + kGradSplitW - 1) / kGradSplitW) * rows * s.L);
+        pmax = std::max(pmax, (qld[i] / kGradSplitU + 1) * s.Lpad * s.N);
+        pmax = std::max(pmax, (int64_t)s.L * sq[i]);
+        dymax = std::max(dymax, (int64_t)s.Lpad * qld[i]);
+    }
+    for (auto &pb : P->banks)
+        for (int j = 1; j < pb.nlev; ++j)
+            gmax = std::max<int64_t>(gmax, 2LL * pb.M * (seg_hi(pb, j, nup, TF) - seg_lo(pb, j, nup)));
+    float *part = nullptr, *dy = nullptr, *g1 = nullptr, *g2 = nullptr;
+    ST_OK(get(&part, (size_t)pmax, false));
+    ST_OK(get(&dy, (size_t)dymax, false));
+    ST_OK(get(&g1, (size_t)std::max<int64_t>(gmax, 1), false));
+    ST_OK(get(&g2, (size_t)std::max<int64_t>(gmax, 1), false));
+    CorrItem *d_items = nullptr;
+    int64_t max_items = 1;
+    for (int i = 0; i < ns; ++i)
+        max_items = std::max(max_items, ((P->slices[i].N + kCorrTQ - 1) / kCorrTQ) * (qld[i] / kGradSplitU + 1));
+    ST_OK(get(&d_items, (size_t)max_items, false));
+
+    std::vector<int64_t> offW(ns), offU(ns);
+    int64_t ow = 0, ou = 0;
+    for (int i = 0; i < ns; ++i) {
+        offW[i] = ow;
+        offU[i] = ou;
+        ow += 2LL * P->banks[P->slices[i].bank].M * P->slices[i].L;
+        ou += (int64_t)P->slices[i].L * P->slices[i].N;
+    }
+    for (size_t b = 0; b < P->banks.size(); ++b) {
+        const PBank &pb = P->banks[b];
+        const int64_t rows = 2LL * pb.M;
+        for (int d = 0; d < ND; ++d) {
+            const float *G = R[b * ND + d];
+            int64_t glo = 0, gn = TF;
+            float *bufs[2] = {g1, g2};
+            for (int j = 0; j < pb.nlev; ++j) {
+                if (j > 0) {
+                    const int p = pb.rates[j - 1] / pb.rates[j];
+                    const int64_t lo = seg_lo(pb, j, nup), n = seg_hi(pb, j, nup, TF) - lo;
+                    float *out = bufs[j & 1];
+                    HIP_OK(launch_upsample_adjoint(st, G, gn, glo, gn, out, n, lo, n, (int32_t)rows, p, nup,
+                                                   P->d_uptaps + (p - 1) * kUpTaps));
+                    G = out;
+                    glo = lo;
+                    gn = n;
+                }
+                for (int i : pb.slices) {
+                    const PSlice &s = P->slices[i];
+                    if (s.level != j) continue;
+                    const float *Y = yseg[i] + (int64_t)d * s.Lpad * qld[i];
+                    // dW = 2 G Y^T
+                    const int64_t nw = (gn + kGradSplitW - 1) / kGradSplitW;
+                    HIP_OK(launch_gemm_f32(st, G, gn, 1, Y, 1, qld[i], rows, s.L, gn, kGradSplitW, part));
+                    HIP_OK(launch_sum_parts(st, part, (int32_t)nw, rows * s.L, (int32_t)rows, s.L, s.L,
+                                            dW + offW[i], s.L, 2.0f, d > 0));
+                    // dY = 2 W^T G  into [Lpad][qld], zero padded
+                    HIP_OK(hipMemsetAsync(dy, 0, sizeof(float) * s.Lpad * qld[i], st));
+                    HIP_OK(launch_gemm_f32(st, s.W32, 1, s.Lpad, G, gn, 1, s.L, gn, rows, rows, part));
+                    HIP_OK(launch_sum_parts(st, part, 1, (int64_t)s.L * gn, s.L, (int32_t)gn, gn, dy, qld[i],
+                                            2.0f, 0));
+                    // dU[l][n] = sum_q dY[l][q] d[q + lo - delay - (N-1) + n]
+                    std::vector<CorrItem> items;
+                    const int64_t nsu = (qld[i] + kGradSplitU - 1) / kGradSplitU;
+                    for (int64_t sp = 0; sp < nsu; ++sp)
+                        for (int c0 = 0; c0 < s.N; c0 += kCorrTQ) {
+                            CorrItem it{};
+                            it.U = dy;
+                            it.ring = dseg[s.D] + d * (dlen[s.D] + 128);
+                            it.part = part + sp * s.Lpad * s.N;
+                            it.off = glo - s.delay - (s.N - 1) - dlo[s.D];
+                            it.Npad = (int32_t)qld[i];
+                            it.Lpad = s.Lpad;
+                            it.cap = (int32_t)dlen[s.D];
+                            it.f = s.N;
+                            it.col0 = c0;
+                            it.ncols = std::min(kCorrTQ, s.N - c0);
+                            it.k0 = (int32_t)(sp * kGradSplitU);
+                            it.klen = (int32_t)std::min<int64_t>(kGradSplitU, qld[i] - sp * kGradSplitU);
+                            it.mb = s.Lpad / 16;
+                            items.push_back(it);
+                        }
+                    HIP_OK(hipMemcpyAsync(d_items, items.data(), sizeof(CorrItem) * items.size(),
+                                          hipMemcpyHostToDevice, st));
+                    LaunchCtx ctx{st, zero};
+                    HIP_OK(launch_corr(ctx, LLOID_FP32, d_items, (int32_t)items.size()));
+                    HIP_OK(launch_sum_parts(st, part, (int32_t)nsu, (int64_t)s.Lpad * s.N, s.L, s.N, s.N,
+                                            dU + offU[i], s.N, 1.0f, d > 0));
+                    HIP_OK(hipStreamSynchronize(st));   // items buffer reused
+                }
+            }
+        }
+    }
+    HIP_OK(hipMemcpyAsync(loss_out, loss_d, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    return LLOID_OK;
+}
+
+lloid_status lloid_set_slice(lloid_plan *P, int32_t slice, const double *U, const double *W, void *stream) {
+    if (!P || !U || !W || slice < 0 || slice >= (int)P->slices.size()) return LLOID_E_ARG;
+    if (P->cfg.normalize) return LLOID_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    PSlice &s = P->slices[slice];
+    const int rows = 2 * P->banks[s.bank].M;
+    if (P->precision == LLOID_FP32) {
+        HIP_OK(launch_convert_rows(st, W, rows, s.L, s.L, nullptr, LLOID_FP32, ROLE_MIXING, s.W32, nullptr, nullptr,
+                                   s.Lpad, nullptr));
+        HIP_OK(launch_convert_rows(st, U, s.L, s.N, s.N, nullptr, LLOID_FP32, ROLE_BASIS, s.U32, nullptr, nullptr,
+                                   s.Npad, nullptr));
+    } else {
+        HIP_OK(launch_convert_rows(st, W, rows, s.L, s.L, nullptr, P->precision, ROLE_MIXING, nullptr, s.Whi, s.Wlo,
+                                   s.Lpad, nullptr));
+        HIP_OK(launch_convert_rows(st, U, s.L, s.N, s.N, nullptr, P->precision, ROLE_BASIS, nullptr, s.Uhi, s.Ulo,
+                                   s.Npad, nullptr));
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    return LLOID_OK;
+}
+
+lloid_status lloid_orthonormalize(double *U, int32_t L, int32_t N, double *W, int32_t rows, void *stream) {
+    if (!U || !W || L < 1 || L > kMaxBasis || N < L || rows < 1) return LLOID_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *G = nullptr;
+    int32_t *info = nullptr;
+    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess) return LLOID_E_NOMEM;
+    if (hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess) {
+        (void)hipFree(G);
+        return LLOID_E_NOMEM;
+    }
+    int32_t h[2] = {0, 0};
+    hipError_t e = launch_cholesky_qr2(st, U, L, N, W, rows, G, info);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(G);
+    (void)hipFree(info);
+    if (e != hipSuccess) return LLOID_E_HIP;
+    return (h[0] || h[1]) ? LLOID_E_STATE : LLOID_OK;
 }
 
 }  // extern "C"

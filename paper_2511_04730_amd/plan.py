@@ -65,6 +65,8 @@ class LloidPlan:
         L.check(self.lib.lloid_plan_create(ctypes.byref(cfg), cbanks, len(banks), st, ctypes.byref(handle)),
                 "lloid_plan_create")
         self.handle = handle
+        self._banks_meta = [[(int(np.shape(s.basis)[0]), int(np.shape(s.basis)[1])) for s in bank.slices]
+                            for bank in banks]
         self.n_banks = self.query(L.Q_N_BANKS)
         self.series_floats = self.query(L.Q_SERIES_FLOATS)
         self.n_peaks = self.query(L.Q_N_PEAKS)
@@ -141,6 +143,48 @@ class LloidPlan:
         return PeakArrays(f[:, 0].reshape(shp).copy(), raw[:, 1].reshape(shp).copy(), f[:, 2].reshape(shp).copy(),
                           f[:, 3].reshape(shp).copy(), raw[:, 4].reshape(shp).copy())
 
+    # ------------------------------------------------------------ gradient
+    def slice_shapes(self):
+        """(2M, L, N) of every slice, banks in order."""
+        out = []
+        for b, bank in enumerate(self._banks_meta):
+            for L_, N_ in bank:
+                out.append((2 * self.bank_templates[b], L_, N_))
+        return out
+
+    def grad(self, strain, target, stream=None):
+        """Loss and gradient of sum (rho - target)^2 over the segment.
+        strain: cuda float32 [n_det, T F]; target: cuda float32
+        [T, series_floats].  Returns (loss, [dW^s], [dU^s]) with views
+        [2M, L] and [L, N] per slice into two packed device tensors."""
+        import torch
+        T = strain.shape[1] // self.sample_rate
+        assert strain.is_cuda and strain.dtype == torch.float32 and strain.is_contiguous()
+        assert tuple(target.shape) == (T, self.series_floats) and target.is_contiguous()
+        shapes = self.slice_shapes()
+        dW = torch.empty(sum(r * l for r, l, _ in shapes), dtype=torch.float32, device="cuda")
+        dU = torch.empty(sum(l * n for _, l, n in shapes), dtype=torch.float32, device="cuda")
+        loss = ctypes.c_double()
+        L.check(self.lib.lloid_grad(self.handle, ctypes.c_void_p(strain.data_ptr()), T,
+                                    ctypes.c_void_p(target.data_ptr()), ctypes.byref(loss),
+                                    ctypes.c_void_p(dW.data_ptr()), ctypes.c_void_p(dU.data_ptr()),
+                                    _stream_handle(stream)), "lloid_grad")
+        gw, gu, ow, ou = [], [], 0, 0
+        for r, l, n in shapes:
+            gw.append(dW[ow:ow + r * l].view(r, l))
+            gu.append(dU[ou:ou + l * n].view(l, n))
+            ow += r * l
+            ou += l * n
+        return float(loss.value), gw, gu
+
+    def set_slice(self, index: int, U, W, stream=None) -> None:
+        """Replace slice `index` with cuda float64 U [L, N] and W [2M, L]."""
+        import torch
+        assert U.is_cuda and W.is_cuda and U.dtype == torch.float64 and W.dtype == torch.float64
+        L.check(self.lib.lloid_set_slice(self.handle, index, ctypes.c_void_p(U.contiguous().data_ptr()),
+                                         ctypes.c_void_p(W.contiguous().data_ptr()), _stream_handle(stream)),
+                "lloid_set_slice")
+
     # ------------------------------------------------------------ timing
     def profile(self, enable: bool = True) -> None:
         """Start (or stop) per-kernel HIP-event timing of push()."""
@@ -183,3 +227,16 @@ class LloidPlan:
 
     def basis_out(self, slice_index: int, n_basis: int, det: int, m_lo: int, m_hi: int) -> np.ndarray:
         return self.inspect(L.INSPECT_BASIS_OUT, slice_index, det, m_lo, m_hi, rows=n_basis)
+
+
+def orthonormalize(U, W, stream=None) -> None:
+    """FP64 CholeskyQR2 on the device, in place: U (cuda float64 [L, N])
+    gets orthonormal rows and W (cuda float64 [rows, L]) is updated so that
+    W U is unchanged."""
+    import torch
+    assert U.is_cuda and W.is_cuda and U.dtype == torch.float64 and W.dtype == torch.float64
+    assert U.is_contiguous() and W.is_contiguous() and W.shape[1] == U.shape[0]
+    lib = L.load()
+    L.check(lib.lloid_orthonormalize(ctypes.c_void_p(U.data_ptr()), U.shape[0], U.shape[1],
+                                     ctypes.c_void_p(W.data_ptr()), W.shape[0], _stream_handle(stream)),
+            "lloid_orthonormalize")

@@ -1,0 +1,167 @@
+"""Gradient of the SNR-reconstruction loss and FP64 re-orthonormalisation
+on the GPU, through the C ABI, against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lloid as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+F = 1024
+SL = [(1024, 0.0, 300, 12), (512, 0.25, 260, 10), (256, 0.75, 300, 8)]
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2511_04730_amd as P
+    return P
+
+
+def _target_layout(rho_rows: np.ndarray, M: int, T: int, n_det: int = 1) -> np.ndarray:
+    """[2M, T F] real rows -> [T, n_det * M * F * 2] per-stride series layout."""
+    z = rho_rows[0::2] + 1j * rho_rows[1::2]                 # [M, T F]
+    z = z.reshape(M, T, F).transpose(1, 0, 2)                # [T, M, F]
+    out = np.stack([z.real, z.imag], axis=-1).reshape(T, M * F * 2)
+    return np.ascontiguousarray(np.tile(out, (1, n_det)).astype(np.float32))
+
+
+@pytest.fixture(scope="module")
+def problem():
+    bank = synth.chirp_bank(F, 10, 25.0, (1.2, 1.5), SL, seed=[13, 1, 0], keep_templates=True)
+    T = 4
+    x = synth.gaussian_strain(13, 1, T * F)
+    cfg = O.OracleConfig(F, normalize=False)
+    target = O.snr_series(x[0], O.direct_bank(bank), cfg, 0, T * F)
+    return bank, x, target, T, cfg
+
+
+def _gpu_series(plan, x, T):
+    """The plan's own forward output per stride, [T, series floats] float64."""
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    plan.reset()
+    out = []
+    for k in range(T):
+        s, _ = plan.push(xs[:, k * F:(k + 1) * F].contiguous())
+        out.append(s.double().cpu().numpy())
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("slices", [SL, [(1024, 0.0, 300, 12), (256, 0.75, 300, 8)]])
+def test_backward_matches_oracle_for_a_given_residual(lib, slices):
+    """The backward arithmetic alone: the target is the plan's own forward
+    output minus a known residual E (the oracle gets its own output minus
+    the same E), so both differentiate the same R = E; 2-rate (x2 stages)
+    and x4-stage banks."""
+    bank = synth.chirp_bank(F, 10, 25.0, (1.2, 1.5), slices, seed=[13, 1, 0], keep_templates=True)
+    T = 4
+    x = synth.gaussian_strain(13, 1, T * F)
+    cfg = O.OracleConfig(F, normalize=False)
+    plan = lib.LloidPlan([bank], F, 1, "fp32", normalize=False)
+    E = np.random.default_rng(3).standard_normal((2 * bank.n_templates, T * F)) * 0.1
+    tg = _gpu_series(plan, x, T) - _target_layout(E, bank.n_templates, T).astype(np.float64)
+    loss, dW, dU = plan.grad(torch.from_numpy(x.astype(np.float32)).cuda(),
+                             torch.from_numpy(tg.astype(np.float32)).cuda())
+    rho = O.snr_series(x[0], bank, cfg, 0, T * F, mixing=[s.mixing for s in bank.slices])
+    L_ref, dW_ref, dU_ref = O.loss_and_grad(x[0], bank, rho - E, cfg, 0, T * F)
+    print(f"loss gpu {loss:.6e} oracle {L_ref:.6e}")
+    assert abs(loss - L_ref) <= 1e-5 * L_ref
+    for s in range(len(bank.slices)):
+        ew = np.abs(dW[s].cpu().numpy() - dW_ref[s]).max() / np.abs(dW_ref[s]).max()
+        eu = np.abs(dU[s].cpu().numpy() - dU_ref[s]).max() / np.abs(dU_ref[s]).max()
+        print(f"slice {s}: dW rel err {ew:.2e}, dU rel err {eu:.2e}")
+        assert ew < 1e-4 and eu < 1e-4
+    assert plan.stride == T
+
+
+def test_gradient_matches_oracle(lib, problem):
+    """Realistic target (the uncompressed bank's output): near the SVD
+    optimum the gradient is a small residual, so the FP32 forward error
+    propagates into it.  Tolerance: 10x the oracle's gradient of a residual
+    of the forward's error size (3e-6 max|rho|, random signs), added to a
+    1e-4 relative term (the gradient is linear in the residual)."""
+    bank, x, target, T, cfg = problem
+    plan = lib.LloidPlan([bank], F, 1, "fp32", normalize=False)
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    tg = torch.from_numpy(_target_layout(target, bank.n_templates, T)).cuda()
+    loss, dW, dU = plan.grad(xs, tg)
+    L_ref, dW_ref, dU_ref = O.loss_and_grad(x[0], bank, target, cfg, 0, T * F)
+    print(f"loss gpu {loss:.6e} oracle {L_ref:.6e}")
+    assert abs(loss - L_ref) <= 1e-4 * L_ref
+    rho = O.snr_series(x[0], bank, cfg, 0, T * F, mixing=[s.mixing for s in bank.slices])
+    noise = 3e-6 * np.abs(rho).max() * np.sign(np.random.default_rng(1).standard_normal(rho.shape))
+    _, dW_n, dU_n = O.loss_and_grad(x[0], bank, rho - noise, cfg, 0, T * F)
+    for s in range(len(bank.slices)):
+        gw, gu = dW[s].cpu().numpy(), dU[s].cpu().numpy()
+        ew, eu = np.abs(gw - dW_ref[s]).max(), np.abs(gu - dU_ref[s]).max()
+        tw = 1e-4 * np.abs(dW_ref[s]).max() + 10 * np.abs(dW_n[s]).max()
+        tu = 1e-4 * np.abs(dU_ref[s]).max() + 10 * np.abs(dU_n[s]).max()
+        print(f"slice {s}: dW err {ew:.2e} (tol {tw:.2e}), dU err {eu:.2e} (tol {tu:.2e})")
+        assert ew < tw and eu < tu
+
+
+def test_gradient_two_detectors_sums(lib, problem):
+    """Detectors share W and U: the gradient is the sum over detectors
+    (given residuals E0, E1 as above)."""
+    bank, x, _, T, cfg = problem
+    x2 = np.concatenate([x, synth.gaussian_strain(14, 1, T * F)])
+    plan = lib.LloidPlan([bank], F, 2, "fp32", normalize=False)
+    g = np.random.default_rng(8)
+    E = [g.standard_normal((2 * bank.n_templates, T * F)) * 0.1 for _ in range(2)]
+    lay = np.concatenate([_target_layout(e, bank.n_templates, T) for e in E], axis=1).astype(np.float64)
+    tg = _gpu_series(plan, x2, T) - lay
+    loss, dW, dU = plan.grad(torch.from_numpy(x2.astype(np.float32)).cuda(),
+                             torch.from_numpy(tg.astype(np.float32)).cuda())
+    mix = [s.mixing for s in bank.slices]
+    L0, W0, U0 = O.loss_and_grad(x2[0], bank, O.snr_series(x2[0], bank, cfg, 0, T * F, mixing=mix) - E[0],
+                                 cfg, 0, T * F)
+    L1, W1, U1 = O.loss_and_grad(x2[1], bank, O.snr_series(x2[1], bank, cfg, 0, T * F, mixing=mix) - E[1],
+                                 cfg, 0, T * F)
+    assert abs(loss - (L0 + L1)) <= 1e-5 * (L0 + L1)
+    for s in range(len(bank.slices)):
+        ref = W0[s] + W1[s]
+        assert np.abs(dW[s].cpu().numpy() - ref).max() < 1e-4 * np.abs(ref).max()
+        ref = U0[s] + U1[s]
+        assert np.abs(dU[s].cpu().numpy() - ref).max() < 1e-4 * np.abs(ref).max()
+
+
+def test_orthonormalize_fp64(lib):
+    g = np.random.default_rng(4)
+    U = g.standard_normal((12, 777)) * np.linspace(1, 3, 12)[:, None]
+    W = g.standard_normal((40, 12))
+    Ut = torch.from_numpy(U.copy()).cuda()
+    Wt = torch.from_numpy(W.copy()).cuda()
+    lib.plan.orthonormalize(Ut, Wt)
+    Q, W2 = Ut.cpu().numpy(), Wt.cpu().numpy()
+    np.testing.assert_allclose(Q @ Q.T, np.eye(12), atol=1e-12)
+    np.testing.assert_allclose(W2 @ Q, W @ U, atol=1e-11 * np.abs(W @ U).max())
+    Qr, Wr = O.cholesky_qr2(U, W)
+    np.testing.assert_allclose(Q, Qr, atol=1e-10)
+    np.testing.assert_allclose(W2, Wr, atol=1e-10 * np.abs(Wr).max())
+
+
+def test_refinement_decreases_loss(lib, problem):
+    """Plain gradient descent with FP64 QR after every step: the loss goes
+    down, the bases stay orthonormal, and the plan filters with the refined
+    slices (its loss equals the oracle's loss of the refined bank)."""
+    from paper_2511_04730_amd.refine import refine
+    bank, x, target, T, cfg = problem
+    plan = lib.LloidPlan([bank], F, 1, "fp32", normalize=False)
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    tg = torch.from_numpy(_target_layout(target, bank.n_templates, T)).cuda()
+    L0, _, _ = plan.grad(xs, tg)
+    # step chosen on the oracle: 3e-5 per unit segment sample scale (T F = 4096)
+    losses, U, W = refine(plan, [bank], xs, tg, steps=20, eta=0.12)
+    print("losses", [f"{v:.4e}" for v in losses[:3]], "...", f"{losses[-1]:.4e}")
+    assert losses[-1] < losses[0]
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:]))
+    for u in U:
+        un = u.cpu().numpy()
+        np.testing.assert_allclose(un @ un.T, np.eye(un.shape[0]), atol=1e-12)
+    ref_bank = synth.Bank(bank.n_templates, [synth.Slice(s.rate, s.delay, u.cpu().numpy(), w.cpu().numpy())
+                                             for s, u, w in zip(bank.slices, U, W)])
+    L_ref = O.loss_only(x[0], ref_bank, target, cfg, 0, T * F)
+    assert abs(losses[-1] - L_ref) <= 1e-4 * L_ref
