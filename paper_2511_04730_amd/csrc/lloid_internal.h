@@ -117,6 +117,11 @@ hipError_t launch_peaks(const LaunchCtx &, const PeakItem *items, int32_t n_item
                         const PartialPeak *partials, lloid_peak *peaks, float threshold,
                         int64_t *stride_ctr_advance);
 hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes);
+size_t mix_lds(int precision, int S);   // dynamic LDS bytes of the mix kernel
+inline size_t mix_lds_bytes(int precision, int S) { return mix_lds(precision, S); }
+// FP8 e4m3 rows with one power-of-two scale per row (basis role of LLOID_FP8_BF16)
+hipError_t launch_convert_fp8_rows(hipStream_t, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
+                                   uint8_t *dst, int32_t dst_ld, float *scale);
 
 // gradient and re-orthonormalisation (lloid_grad.hip)
 hipError_t launch_copy_window(hipStream_t, const float *ring, int64_t ring_ld, int32_t cap, int64_t a,

@@ -8,7 +8,7 @@
 //   reduce    fixed-order sum of the tap splits into the basis-output ring
 //   mix       mixing-matrix contraction on MFMA fused with the polyphase
 //             upsample-and-add chain (lowest rate first), the SNR series
-//             write and per-tile peak candidates
+//             write and per-tile peak candidates (lloid_mix.hip)
 //   peaks     fixed-order reduction of the candidates, one trigger per
 //             template (Sec. II.D.1)
 // Every output element has exactly one owner and every sum has a fixed
@@ -17,15 +17,12 @@
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 
+#include "lloid_device.h"
 #include "lloid_internal.h"
 #include "lloid_mfma.h"
 
 namespace lloid {
 
-__device__ __forceinline__ int64_t posmod(int64_t a, int64_t m) {
-    int64_t r = a % m;
-    return r < 0 ? r + m : r;
-}
 
 // ------------------------------------------------------------------ ingest
 __global__ void ingest_kernel(const float *__restrict__ strain, int64_t src_det_stride, uint32_t gap_mask,
@@ -218,30 +215,53 @@ __global__ __launch_bounds__(256) void corr16_kernel(const CorrItem *__restrict_
     for (int m = 0; m < MBMAX; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
-    for (int kk = 0; kk < it.klen; kk += TK) {
-        __syncthreads();
-        for (int e = tid; e < rows * (TK / 8); e += 256) {
-            const int r = e / (TK / 8), c8 = e % (TK / 8);
-            const int64_t g = (int64_t)r * it.Npad + it.k0 + kk + 8 * c8;
-            *reinterpret_cast<uint4 *>(&Uh[r * US + 8 * c8]) = *reinterpret_cast<const uint4 *>(gh + g);
-            if (SPLIT_U)
-                *reinterpret_cast<uint4 *>(&Ul[r * US + 8 * c8]) = *reinterpret_cast<const uint4 *>(gl + g);
+    // the next stage's basis tile and strain element are fetched into
+    // registers while the current stage's MFMAs run from LDS
+    constexpr int PER = (MBMAX * 16 * (TK / 8) + 255) / 256;
+    uint4 uh[PER], ul[PER];
+    float dv = 0.0f;
+    auto gload = [&](int kk) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < rows * (TK / 8)) {
+                const int r = e / (TK / 8), c8 = e % (TK / 8);
+                const int64_t g = (int64_t)r * it.Npad + it.k0 + kk + 8 * c8;
+                uh[i] = *reinterpret_cast<const uint4 *>(gh + g);
+                if (SPLIT_U) ul[i] = *reinterpret_cast<const uint4 *>(gl + g);
+            }
         }
-        const int64_t p0 = posmod(dbase + kk, it.cap);
-        for (int e = tid; e < kCorrTQ + TK; e += 256) {
-            const float v = it.ring[p0 + e];
-            const T h = (T)v;
-            const T l = (T)(v - (float)h);
+        if (tid < kCorrTQ + TK) dv = it.ring[posmod(dbase + kk, it.cap) + tid];
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < rows * (TK / 8)) {
+                const int r = e / (TK / 8), c8 = e % (TK / 8);
+                *reinterpret_cast<uint4 *>(&Uh[r * US + 8 * c8]) = uh[i];
+                if (SPLIT_U) *reinterpret_cast<uint4 *>(&Ul[r * US + 8 * c8]) = ul[i];
+            }
+        }
+        if (tid < kCorrTQ + TK) {
+            const T h = (T)dv;
+            const T l = (T)(dv - (float)h);
 #pragma unroll
             for (int s = 0; s < 8; ++s) {
-                const int i = e - s;
+                const int i = tid - s;
                 if (i >= 0 && i < DL) {
                     Dh[s * DL + i] = h;
                     Dl[s * DL + i] = l;
                 }
             }
         }
+    };
+    gload(0);
+    for (int kk = 0; kk < it.klen; kk += TK) {
         __syncthreads();
+        lstore();
+        __syncthreads();
+        if (kk + TK < it.klen) gload(kk + TK);
 #pragma unroll
         for (int ks = 0; ks < TK; ks += 32) {
             const int idx = wave * 16 + li + ks + 8 * lk;
@@ -275,8 +295,150 @@ __global__ __launch_bounds__(256) void corr16_kernel(const CorrItem *__restrict_
     }
 }
 
+// FP8 correlation on v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3 on gfx950): the
+// basis rows hold e4m3(u_l 2^e_l) with a power-of-two scale per basis vector
+// chosen at plan time (largest |u| near the e4m3 maximum 448); the strain is
+// scaled by kFp8StrainScale and split into two e4m3 parts, d = d_hi + d_lo.
+// Eight consecutive taps per lane are one 64-bit operand; the Hankel side
+// again comes from eight shifted LDS copies.  Output rows are rescaled by
+// uscale[l] = 2^-e_l / kFp8StrainScale.
+constexpr float kFp8StrainScale = 8.0f;
+
+__device__ __forceinline__ uint32_t fp8_byte(float v) {
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xffu;
+}
+__device__ __forceinline__ float fp8_value(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
+
+__global__ __launch_bounds__(256) void corr8_kernel(const CorrItem *__restrict__ items,
+                                                    const int64_t *__restrict__ stride_ctr) {
+    constexpr int TK = 64;
+    constexpr int US = TK + 16;            // bytes per basis row in LDS
+    constexpr int MBMAX = kMaxBasis / 16;
+    constexpr int DL = kCorrTQ + TK + 8;   // bytes per shifted copy
+    __shared__ __attribute__((aligned(16))) uint8_t U8[MBMAX * 16 * US];
+    __shared__ __attribute__((aligned(16))) uint8_t Dh[8 * DL];
+    __shared__ __attribute__((aligned(16))) uint8_t Dl[8 * DL];
+    const CorrItem it = items[blockIdx.x];
+    const int64_t kstr = *stride_ctr;
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int li = lane & 15, lk = lane >> 4;
+    const int rows = it.mb * 16;
+    const uint8_t *gu = static_cast<const uint8_t *>(it.Uhi);
+
+    floatx4 acc[MBMAX];
+#pragma unroll
+    for (int m = 0; m < MBMAX; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
+    constexpr int PER = (MBMAX * 16 * (TK / 8) + 255) / 256;
+    uint2 ur[PER];
+    float dv = 0.0f;
+    auto gload = [&](int kk) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < rows * (TK / 8)) {
+                const int r = e / (TK / 8), c8 = e % (TK / 8);
+                ur[i] = *reinterpret_cast<const uint2 *>(gu + (int64_t)r * it.Npad + it.k0 + kk + 8 * c8);
+            }
+        }
+        if (tid < kCorrTQ + TK) dv = it.ring[posmod(dbase + kk, it.cap) + tid];
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < rows * (TK / 8)) {
+                const int r = e / (TK / 8), c8 = e % (TK / 8);
+                *reinterpret_cast<uint2 *>(&U8[r * US + 8 * c8]) = ur[i];
+            }
+        }
+        if (tid < kCorrTQ + TK) {
+            // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
+            const float v = fminf(fmaxf(dv * kFp8StrainScale, -448.0f), 448.0f);
+            const uint32_t h = fp8_byte(v);
+            const uint32_t l = fp8_byte(v - fp8_value(h));
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int i = tid - s;
+                if (i >= 0 && i < DL) {
+                    Dh[s * DL + i] = (uint8_t)h;
+                    Dl[s * DL + i] = (uint8_t)l;
+                }
+            }
+        }
+    };
+    gload(0);
+    for (int kk = 0; kk < it.klen; kk += TK) {
+        __syncthreads();
+        lstore();
+        __syncthreads();
+        if (kk + TK < it.klen) gload(kk + TK);
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 32) {
+            const int idx = wave * 16 + li + ks + 8 * lk;
+            const int sft = idx & 7;
+            const long bh = *reinterpret_cast<const long *>(&Dh[sft * DL + idx - sft]);
+            const long bl = *reinterpret_cast<const long *>(&Dl[sft * DL + idx - sft]);
+#pragma unroll
+            for (int m = 0; m < MBMAX; ++m) {
+                if (m < it.mb) {
+                    const long a = *reinterpret_cast<const long *>(&U8[(m * 16 + li) * US + ks + 8 * lk]);
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bl, acc[m], 0, 0, 0);
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bh, acc[m], 0, 0, 0);
+                }
+            }
+        }
+    }
+    const int c = wave * 16 + li;
+    if (c < it.ncols) {
+#pragma unroll
+        for (int m = 0; m < MBMAX; ++m) {
+            if (m < it.mb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int r = m * 16 + lk * 4 + v;
+                    it.part[(int64_t)r * it.f + it.col0 + c] = acc[m][v] * it.uscale[r];
+                }
+            }
+        }
+    }
+}
+
+// Basis rows to e4m3 with a power-of-two scale per row: one block per row,
+// e = floor(log2(448 / max|u|)); dst = e4m3(u 2^e); scale[r] = 2^-e / kFp8StrainScale.
+__global__ __launch_bounds__(256) void convert_fp8_rows_kernel(const double *__restrict__ src, int32_t cols,
+                                                               int32_t src_ld, uint8_t *__restrict__ dst,
+                                                               int32_t dst_ld, float *__restrict__ scale) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
+    double mx = 0.0;
+    for (int c = threadIdx.x; c < cols; c += 256) mx = fmax(mx, fabs(src[(int64_t)r * src_ld + c]));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const int e = red[0] > 0.0 ? (int)floor(log2(448.0 / red[0])) : 0;
+    const double s = ldexp(1.0, e);
+    for (int c = threadIdx.x; c < cols; c += 256)
+        dst[(int64_t)r * dst_ld + c] = (uint8_t)fp8_byte((float)(src[(int64_t)r * src_ld + c] * s));
+    if (threadIdx.x == 0) scale[r] = (float)(ldexp(1.0, -e) / kFp8StrainScale);
+}
+
+hipError_t launch_convert_fp8_rows(hipStream_t st, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
+                                   uint8_t *dst, int32_t dst_ld, float *scale) {
+    hipLaunchKernelGGL(convert_fp8_rows_kernel, dim3(rows), dim3(256), 0, st, src, cols, src_ld, dst, dst_ld, scale);
+    return hipGetLastError();
+}
+
 hipError_t launch_corr_reduced(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items) {
     switch (precision) {
+        case LLOID_FP8_BF16:
+            hipLaunchKernelGGL(corr8_kernel, dim3(n_items), dim3(256), 0, ctx.stream, items, ctx.stride_ctr);
+            break;
         case LLOID_BF16X3:
             hipLaunchKernelGGL((corr16_kernel<__bf16, bf16x8, true>), dim3(n_items), dim3(256), 0, ctx.stream, items,
                                ctx.stride_ctr);
@@ -324,349 +486,9 @@ hipError_t launch_reduce(const LaunchCtx &ctx, const ReduceItem *items, int32_t 
     return hipGetLastError();
 }
 
-// ------------------------------------------- mixing + upsample-and-add chain
-// One work group = 32 real rows (16 templates) x kMixTN top-rate samples of
-// one bank and detector.  Levels run lowest rate first; level j covers the
-// local window [lo_j + t0/P_j, +n_j): the tile plus the polyphase halo its
-// upper level reads.  Per level:
-//   acc = H_up(level j+1)  (Eq. (upsample), zero-phase: phase-0 samples are
-//                            copied, others take 2 N_up + 1 taps)
-//       + sum over slices at rate j of W~^s (rows) x y^s (window)   [MFMA]
-// Level j >= 1 is kept in LDS for the next level; level 0 goes to the SNR
-// series (interleaved re, im) and to per-lane running peaks.  The W~ rows of
-// all slices of a level are staged together in LDS (row stride SW chosen so
-// a half-wave's fragment reads hit distinct banks); level buffers use row
-// stride S = 2 mod 32.
-//
-// The polyphase upsample is a banded contraction into the same MFMA
-// accumulator: for the 16 output columns of a block starting at level index
-// i0, with q0 = floor(i0/p) and lane column c (i = i0 + c, q = floor(i/p),
-// ph = i mod p, off = q - q0),
-//   H_up(prev)[r][c] = sum_k prev[r][q0 - N_up + k] Ker[k][c],
-//   Ker[k][c] = z_ph[off + 2 N_up - k]  for off <= k <= off + 2 N_up, else 0,
-// and for phase 0 Ker is the unit vector at k = off + N_up (the copy case of
-// Eq. (upsample)).  off <= 7 and 2 N_up <= 16, so a 24- (FP32) or 32-wide
-// (16-bit) window of prev holds every tap.
-struct PeakCand {
-    float p2;
-    int idx;
-    float re, im;
-};
-
-__device__ __forceinline__ bool better(float p2, int idx, float bp2, int bidx) {
-    return p2 > bp2 || (p2 == bp2 && idx < bidx);
-}
-
-__device__ __forceinline__ float ker_value(int k, int off, int ph, int nup, const float *__restrict__ taps) {
-    if (ph == 0) return k == off + nup ? 1.0f : 0.0f;
-    const int t = off + 2 * nup - k;
-    return (t >= 0 && t <= 2 * nup) ? taps[ph * kUpTaps + t] : 0.0f;
-}
-
-struct UpArgs {
-    const float *prev;       // level j+1 buffer, row stride S
-    int S, n_prev, m0;       // m0: buffer index of the window start
-    int off, ph, nup;
-    const float *taps;       // sub-kernels of this stage, [p][kUpTaps]
-    bool valid;
-};
-
-template <typename Op>
-__global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ items, const MixBank *__restrict__ banks,
-                                                  const MixSlice *__restrict__ slices,
-                                                  const float *__restrict__ uptaps, float *__restrict__ series,
-                                                  PartialPeak *__restrict__ partials, int32_t F, int32_t n_det,
-                                                  int32_t S, int32_t SW, int32_t nup,
-                                                  const int64_t *__restrict__ stride_ctr) {
-    extern __shared__ float sm[];
-    constexpr int TM = kMixTM;
-    float *bufA = sm;
-    float *bufB = sm + TM * S;
-    float *Ws = sm + 2 * TM * S;
-    __shared__ PeakCand wbest[4][TM / 2];
-
-    const MixItem it = items[blockIdx.x];
-    const MixBank &B = banks[it.bank];
-    const int64_t k = *stride_ctr;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lg = lane >> 4;
-
-    float *prev = bufA, *cur = bufB;
-    int lo_prev = 0;
-    PeakCand best[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) best[t] = PeakCand{-1.0f, 0x7fffffff, 0.f, 0.f};
-
-    for (int j = B.nlev - 1; j >= 0; --j) {
-        const int lo = B.lo[j] + it.t0 / B.P[j];
-        const int n = B.n[j];
-        const int64_t abs0 = k * (int64_t)B.rate[j] + lo;
-        __syncthreads();   // previous level complete; Ws free
-        // stage the W~ rows of every slice at this level
-        int lsum = 0;
-        for (int s = B.slice_begin[j]; s < B.slice_begin[j + 1]; ++s) {
-            const MixSlice &ms = slices[s];
-            Op::stage_w(ms, it.r0, Ws, SW, lsum, tid);
-            lsum += ms.Lpad;
-        }
-        __syncthreads();
-        const bool has_up = (j < B.nlev - 1);
-        const int logp = has_up ? __ffs(B.p[j + 1]) - 1 : 0;
-        const float *taps = has_up ? uptaps + (B.p[j + 1] - 1) * kUpTaps : nullptr;
-        const int n_prev = has_up ? B.n[j + 1] : 0;
-        const int nb = (n + 15) >> 4;
-        for (int cb = wave; cb < nb; cb += 4) {
-            const int c = cb * 16 + li;
-            const bool valid = c < n;
-            floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
-            int lb = 0;
-            for (int s = B.slice_begin[j]; s < B.slice_begin[j + 1]; ++s) {
-                const MixSlice &ms = slices[s];
-                const float *Y = ms.Y + (int64_t)it.det * ms.ydet;
-                const int64_t pos0 = posmod(abs0, ms.capY) + c;
-                Op::contract(Y, ms, pos0, valid, Ws, SW, lb, li, lg, acc);
-                lb += ms.Lpad;
-            }
-            if (has_up) {
-                const int i0 = lo + cb * 16;
-                const int q0 = i0 >> logp;   // arithmetic shift: floor for negative indices
-                const int i = i0 + li;
-                UpArgs ua{prev, S, n_prev, q0 - nup - lo_prev, (i >> logp) - q0, i & ((1 << logp) - 1), nup,
-                          taps, valid};
-                Op::upsample(ua, li, lg, acc);
-            }
-            if (!valid) continue;
-            if (j > 0) {
-#pragma unroll
-                for (int m = 0; m < 2; ++m)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) cur[(m * 16 + lg * 4 + v) * S + c] = acc[m][v];
-            }
-            if (j == 0) {
-                const int t = it.t0 + c;
-#pragma unroll
-                for (int m = 0; m < 2; ++m) {
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float re = acc[m][2 * h], im = acc[m][2 * h + 1];
-                        const int tl = m * 8 + lg * 2 + h;   // template within the tile
-                        const int tmpl = it.r0 / 2 + tl;
-                        if (series && tmpl < B.M) {
-                            float2 *o = reinterpret_cast<float2 *>(series + B.series_off) +
-                                        ((int64_t)it.det * B.M + tmpl) * F + t;
-                            *o = make_float2(re, im);
-                        }
-                        const float p2 = re * re + im * im;
-                        if (better(p2, t, best[m * 2 + h].p2, best[m * 2 + h].idx))
-                            best[m * 2 + h] = PeakCand{p2, t, re, im};
-                    }
-                }
-            }
-        }
-        float *tmp = prev;
-        prev = cur;
-        cur = tmp;
-        lo_prev = lo;
-    }
-    // peak candidates: reduce over the 16 lanes of a row group, then waves
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        PeakCand b = best[q];
-        for (int off = 1; off < 16; off <<= 1) {
-            PeakCand o;
-            o.p2 = __shfl_xor(b.p2, off, 64);
-            o.idx = __shfl_xor(b.idx, off, 64);
-            o.re = __shfl_xor(b.re, off, 64);
-            o.im = __shfl_xor(b.im, off, 64);
-            if (better(o.p2, o.idx, b.p2, b.idx)) b = o;
-        }
-        if (li == 0) wbest[wave][(q >> 1) * 8 + lg * 2 + (q & 1)] = b;
-    }
-    __syncthreads();
-    if (tid < TM / 2) {
-        PeakCand b = wbest[0][tid];
-        for (int w = 1; w < 4; ++w) {
-            const PeakCand o = wbest[w][tid];
-            if (better(o.p2, o.idx, b.p2, b.idx)) b = o;
-        }
-        const int tmpl = it.r0 / 2 + tid;
-        if (tmpl < B.M) {
-            const int64_t pi = B.part_off + ((int64_t)it.det * B.M + tmpl) * B.n_ttiles + it.t0 / kMixTN;
-            partials[pi] = PartialPeak{b.p2, b.idx, b.re, b.im};
-        }
-    }
-}
-
-struct MixF32 {
-    static __device__ __forceinline__ void stage_w(const MixSlice &ms, int r0, float *Ws, int SW, int lbase, int tid) {
-        const int Lp = ms.Lpad;
-        for (int e = tid; e < kMixTM * Lp; e += 256) {
-            const int r = e / Lp, l = e % Lp;
-            Ws[r * SW + lbase + l] = ms.W[(int64_t)(r0 + r) * Lp + l];
-        }
-    }
-    // All basis-output loads of the column block are issued before the first
-    // MFMA, so their latency is paid once per block, not once per k-step.
-    static __device__ __forceinline__ void contract(const float *Y, const MixSlice &ms, int64_t pos0, bool valid,
-                                                    const float *Ws, int SW, int lb, int li, int lg,
-                                                    floatx4 (&acc)[2]) {
-        constexpr int KS = kMaxBasis / 4;
-        const int64_t rs = 2 * (int64_t)ms.capY;
-        const int nks = ms.Lpad >> 2;
-        float bv[KS];
-#pragma unroll
-        for (int t = 0; t < KS; ++t) bv[t] = (valid && t < nks) ? Y[(int64_t)(4 * t + lg) * rs + pos0] : 0.0f;
-#pragma unroll
-        for (int t = 0; t < KS; ++t) {
-            if (t < nks) {
-                const float a0 = Ws[li * SW + lb + 4 * t + lg];
-                const float a1 = Ws[(16 + li) * SW + lb + 4 * t + lg];
-                acc[0] = mfma_16x16x4_f32(a0, bv[t], acc[0]);
-                acc[1] = mfma_16x16x4_f32(a1, bv[t], acc[1]);
-            }
-        }
-    }
-    // 24-wide window, six K-steps of 4
-    static __device__ __forceinline__ void upsample(const UpArgs &u, int li, int lg, floatx4 (&acc)[2]) {
-#pragma unroll
-        for (int t = 0; t < 6; ++t) {
-            const int kk = 4 * t + lg;
-            const float b = u.valid ? ker_value(kk, u.off, u.ph, u.nup, u.taps) : 0.0f;
-            const int idx = min(u.m0 + kk, u.n_prev - 1);
-            const float a0 = u.prev[li * u.S + idx];
-            const float a1 = u.prev[(16 + li) * u.S + idx];
-            acc[0] = mfma_16x16x4_f32(a0, b, acc[0]);
-            acc[1] = mfma_16x16x4_f32(a1, b, acc[1]);
-        }
-    }
-};
-
-// 16-bit mixing on v_mfma_f32_16x16x32_{bf16,f16}.  The W~ rows are staged in
-// LDS as T (hi part, then lo part at offset 32 SW), row stride SW = 8 mod 64
-// elements so each 16-B fragment read of a half-wave hits distinct banks.  The
-// basis outputs are FP32 in the ring and are split on the fly:
-// y = y_hi + y_lo, y_hi = T(y), y_lo = T(y - y_hi).
-//   SPLIT_W (bf16x3): W_hi y_lo + W_lo y_hi + W_hi y_hi
-//   otherwise (fp16): W y_lo + W y_hi
-template <typename T, typename T8, bool SPLIT_W>
-struct Mix16 {
-    static __device__ __forceinline__ T8 mfma_in(const T *p) { return *reinterpret_cast<const T8 *>(p); }
-    static __device__ __forceinline__ void stage_w(const MixSlice &ms, int r0, float *Wsf, int SW, int lbase,
-                                                   int tid) {
-        T *wh = reinterpret_cast<T *>(Wsf);
-        T *wl = wh + kMixTM * SW;
-        const int Lp = ms.Lpad;
-        const T *gh = static_cast<const T *>(ms.Whi);
-        const T *gl = static_cast<const T *>(ms.Wlo);
-        for (int e = tid; e < kMixTM * Lp; e += 256) {
-            const int r = e / Lp, l = e % Lp;
-            wh[r * SW + lbase + l] = gh[(int64_t)(r0 + r) * Lp + l];
-            if (SPLIT_W) wl[r * SW + lbase + l] = gl[(int64_t)(r0 + r) * Lp + l];
-        }
-    }
-    static __device__ __forceinline__ void contract(const float *Y, const MixSlice &ms, int64_t pos0, bool valid,
-                                                    const float *Wsf, int SW, int lb, int li, int lg,
-                                                    floatx4 (&acc)[2]) {
-        constexpr int KS = kMaxBasis / 32;
-        const T *wh = reinterpret_cast<const T *>(Wsf);
-        const T *wl = wh + kMixTM * SW;
-        const int64_t rs = 2 * (int64_t)ms.capY;
-        const int nks = ms.Lpad >> 5;
-        float yv[KS][8];
-#pragma unroll
-        for (int t = 0; t < KS; ++t)
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                yv[t][j] = (valid && t < nks) ? Y[(int64_t)(32 * t + 8 * lg + j) * rs + pos0] : 0.0f;
-#pragma unroll
-        for (int t = 0; t < KS; ++t) {
-            if (t < nks) {
-                T8 bh, bl;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const T h = (T)yv[t][j];
-                    bh[j] = h;
-                    bl[j] = (T)(yv[t][j] - (float)h);
-                }
-#pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    const int off = (m * 16 + li) * SW + lb + 32 * t + 8 * lg;
-                    const T8 ah = mfma_in(wh + off);
-                    acc[m] = mfma16(ah, bl, acc[m]);
-                    if (SPLIT_W) acc[m] = mfma16(mfma_in(wl + off), bh, acc[m]);
-                    acc[m] = mfma16(ah, bh, acc[m]);
-                }
-            }
-        }
-    }
-    // 32-wide window, one K-step; both operands split (three products), so
-    // the interpolation keeps ~16 (bf16) or ~22 (fp16) significant bits
-    static __device__ __forceinline__ void upsample(const UpArgs &u, int li, int lg, floatx4 (&acc)[2]) {
-        T8 kh, kl;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const float kv = u.valid ? ker_value(8 * lg + j, u.off, u.ph, u.nup, u.taps) : 0.0f;
-            const T h = (T)kv;
-            kh[j] = h;
-            kl[j] = (T)(kv - (float)h);
-        }
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            T8 ph, pl;
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int idx = min(u.m0 + 8 * lg + j, u.n_prev - 1);
-                const float pv = u.prev[(m * 16 + li) * u.S + idx];
-                const T h = (T)pv;
-                ph[j] = h;
-                pl[j] = (T)(pv - (float)h);
-            }
-            acc[m] = mfma16(ph, kl, acc[m]);
-            acc[m] = mfma16(pl, kh, acc[m]);
-            acc[m] = mfma16(ph, kh, acc[m]);
-        }
-    }
-};
-
-// Raise the dynamic-LDS limit of the kernels whose tiles depend on the plan
-// (gfx950 has 160 KB of LDS per work group).
-hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(down_kernel),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)down_bytes);
-    if (e != hipSuccess) return e;
-    const void *mix = nullptr;
-    switch (precision) {
-        case LLOID_FP32: mix = reinterpret_cast<const void *>(mix_kernel<MixF32>); break;
-        case LLOID_BF16X3: mix = reinterpret_cast<const void *>(mix_kernel<Mix16<__bf16, bf16x8, true>>); break;
-        case LLOID_FP16: mix = reinterpret_cast<const void *>(mix_kernel<Mix16<_Float16, halfx8, false>>); break;
-        default: return hipErrorNotSupported;
-    }
-    return hipFuncSetAttribute(mix, hipFuncAttributeMaxDynamicSharedMemorySize, (int)mix_bytes);
-}
-
-hipError_t launch_mix(const LaunchCtx &ctx, int precision, const MixItem *items, int32_t n_items,
-                      const MixBank *banks, const MixSlice *slices, const float *uptaps, float *series,
-                      PartialPeak *partials, int32_t F, int32_t n_det, int32_t S, int32_t SW, int32_t nup) {
-    if (n_items == 0) return hipSuccess;
-    const size_t lds = (size_t)(2 * kMixTM * S + kMixTM * SW) * sizeof(float);
-    switch (precision) {
-        case LLOID_FP32:
-            hipLaunchKernelGGL(mix_kernel<MixF32>, dim3(n_items), dim3(256), lds, ctx.stream, items, banks, slices,
-                               uptaps, series, partials, F, n_det, S, SW, nup, ctx.stride_ctr);
-            break;
-        case LLOID_BF16X3:
-            hipLaunchKernelGGL((mix_kernel<Mix16<__bf16, bf16x8, true>>), dim3(n_items), dim3(256), lds, ctx.stream,
-                               items, banks, slices, uptaps, series, partials, F, n_det, S, SW, nup, ctx.stride_ctr);
-            break;
-        case LLOID_FP16:
-            hipLaunchKernelGGL((mix_kernel<Mix16<_Float16, halfx8, false>>), dim3(n_items), dim3(256), lds,
-                               ctx.stream, items, banks, slices, uptaps, series, partials, F, n_det, S, SW, nup,
-                               ctx.stride_ctr);
-            break;
-        default:
-            return hipErrorNotSupported;
-    }
-    return hipGetLastError();
+hipError_t configure_down_lds(size_t down_bytes) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(down_kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)down_bytes);
 }
 
 // ----------------------------------------------------------------- peaks
@@ -741,7 +563,7 @@ hipError_t launch_convert_reduced(hipStream_t st, const double *src, int32_t row
     (void)row_scale_out;
     const int64_t n = (int64_t)rows * cols;
     const dim3 grid((unsigned)((n + 255) / 256));
-    if (precision == LLOID_BF16X3) {
+    if (precision == LLOID_BF16X3 || precision == LLOID_FP8_BF16) {
         hipLaunchKernelGGL(convert_split_kernel<__bf16>, grid, dim3(256), 0, st, src, rows, cols, src_ld, row_scale,
                            static_cast<__bf16 *>(dst_hi), static_cast<__bf16 *>(dst_lo), dst_ld);
     } else if (precision == LLOID_FP16) {

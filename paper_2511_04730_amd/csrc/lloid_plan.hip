@@ -118,6 +118,7 @@ struct lloid_plan {
     lloid_peak *g_peaks = nullptr;
     uint32_t g_gap = 0;
     double flops = 0.0;
+    int ksplit = kCorrSplitK;      // taps per correlation work item
 
     // per-kernel event timing (lloid_profile_*)
     bool profiling = false;
@@ -233,7 +234,6 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
     if (!out) return LLOID_E_ARG;
     *out = nullptr;
     ST_OK(validate(config, banks, n_banks));
-    if (config->precision == LLOID_FP8_BF16) return LLOID_E_UNSUPPORTED;
     hipStream_t st = static_cast<hipStream_t>(stream);
 
     lloid_plan *P = new (std::nothrow) lloid_plan();
@@ -313,6 +313,23 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         P->total_templates += pb.M;
     }
     P->series_floats = series_off;
+
+    // Tap split of the correlation: the largest of 8192..512 that still gives
+    // at least 2048 work items (8 per CU); longer splits write fewer partial
+    // planes for the reduction to read back.
+    {
+        P->ksplit = kCorrSplitK;
+        for (int cand = 8192; cand >= kCorrSplitK; cand /= 2) {
+            int64_t items = 0;
+            for (auto &s : P->slices)
+                items += (int64_t)ND * ((s.rate + kCorrTQ - 1) / kCorrTQ) * ((s.Npad + cand - 1) / cand);
+            if (items >= 2048) {
+                P->ksplit = cand;
+                break;
+            }
+        }
+        for (auto &s : P->slices) s.nsplit = (s.Npad + P->ksplit - 1) / P->ksplit;
+    }
     P->n_peaks = peak_off;
 
     // ---------------------------------------------------------- rings
@@ -383,16 +400,25 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                 } else {
                     // 16-bit parts: hi and lo of W (bf16x3) or W alone (fp16);
                     // hi and lo of U (bf16x3) or U alone (fp16)
-                    const bool split = P->precision == LLOID_BF16X3;
+                    const bool split = P->precision != LLOID_FP16;   // bf16x3 mixing for BF16X3 and FP8_BF16
                     uint16_t *wh = nullptr, *wl = nullptr, *uh = nullptr, *ul = nullptr;
                     ST_OK(P->alloc(&wh, (size_t)pb.rows_pad * ps.Lpad));
                     if (split) ST_OK(P->alloc(&wl, (size_t)pb.rows_pad * ps.Lpad));
-                    ST_OK(P->alloc(&uh, (size_t)ps.Lpad * ps.Npad));
-                    if (split) ST_OK(P->alloc(&ul, (size_t)ps.Lpad * ps.Npad));
                     HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, P->precision, ROLE_MIXING, nullptr,
                                                wh, wl, ps.Lpad, nullptr));
-                    HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, P->precision, ROLE_BASIS, nullptr,
-                                               uh, ul, ps.Npad, nullptr));
+                    if (P->precision == LLOID_FP8_BF16) {
+                        // e4m3 basis, one power-of-two scale per basis vector
+                        uint8_t *u8 = nullptr;
+                        ST_OK(P->alloc(&u8, (size_t)ps.Lpad * ps.Npad));
+                        ST_OK(P->alloc(&ps.uscale, (size_t)ps.Lpad));
+                        HIP_OK(launch_convert_fp8_rows(st, u64, ps.L, ps.N, ps.N, u8, ps.Npad, ps.uscale));
+                        uh = reinterpret_cast<uint16_t *>(u8);
+                    } else {
+                        ST_OK(P->alloc(&uh, (size_t)ps.Lpad * ps.Npad));
+                        if (P->precision == LLOID_BF16X3) ST_OK(P->alloc(&ul, (size_t)ps.Lpad * ps.Npad));
+                        HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, P->precision, ROLE_BASIS,
+                                                   nullptr, uh, ul, ps.Npad, nullptr));
+                    }
                     ps.Whi = wh;
                     ps.Wlo = wl;
                     ps.Uhi = uh;
@@ -479,8 +505,8 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
             const int f = s.rate;
             for (int det = 0; det < ND; ++det) {
                 for (int sp = 0; sp < s.nsplit; ++sp) {
-                    const int k0 = sp * kCorrSplitK;
-                    const int klen = std::min(kCorrSplitK, s.Npad - k0);
+                    const int k0 = sp * P->ksplit;
+                    const int klen = std::min(P->ksplit, s.Npad - k0);
                     for (int c0 = 0; c0 < f; c0 += kCorrTQ) {
                         CorrItem it{};
                         it.U = s.U32;
@@ -574,12 +600,18 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         }
         for (auto &kv : P->rings)
             if (kv.first > 1) P->flops += (double)ND * (F / kv.first) * 2.0 * (2 * kv.first * ndown + 1);
-        P->mixS = (int)round_up(std::max(S, 1), 32) + 2;    // 2 mod 32
-        // W staging row stride: FP32 words 2 mod 32; 16-bit elements 8 mod 64
-        P->mixSW = P->precision == LLOID_FP32 ? (int)round_up(std::max(SW, 16), 32) + 2
-                                              : (int)round_up(std::max(SW, 32), 32) + 8;
-        const size_t mix_lds = (size_t)(2 * kMixTM * P->mixS + kMixTM * P->mixSW) * 4;
-        if (mix_lds > (size_t)kMaxLdsBytes) return LLOID_E_UNSUPPORTED;
+        // level-buffer row stride: >= the widest lower-level window, 2 or 18
+        // mod 32 words (the upsample's 16 rows x 2 columns per half-wave hit
+        // distinct banks); every window must fit one 256-thread row load
+        if (S > kMixTN) return LLOID_E_UNSUPPORTED;
+        {
+            int s2 = std::max(S, 1);
+            while (s2 % 32 != 2 && s2 % 32 != 18) ++s2;
+            P->mixS = s2;
+        }
+        P->mixSW = SW;
+        const size_t mix_lds = mix_lds_bytes(P->precision, P->mixS);
+        if (mix_lds == 0 || mix_lds > (size_t)kMaxLdsBytes) return LLOID_E_UNSUPPORTED;
         HIP_OK(configure_lds(P->precision, mix_lds, (size_t)P->down_lds * 4));
         P->n_mix = (int)items.size();
         P->n_peakitems = (int)pk.size();

@@ -1,6 +1,9 @@
-"""Reduced-precision forms (BF16x3, FP16 with split strain and basis
-outputs) against the FP64 oracle: SNR error within 1e-3 (relative above the
-trigger threshold, absolute / 4 below), triggers consistent."""
+"""Reduced-precision forms against the FP64 oracle.  BF16x3 and FP16 (split
+strain and basis outputs) keep the SNR error within 1e-3 (relative above the
+trigger threshold, absolute / 4 below); FP8 (e4m3 basis with a power-of-two
+scale per basis vector, split e4m3 strain, BF16x3 mixing) has the stated
+bound 5e-2, set by the 3-bit mantissa of the basis.  Triggers consistent
+within the measured error."""
 import numpy as np
 import pytest
 
@@ -12,8 +15,7 @@ from test_gpu_parity import _ragged_banks
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
-GATE = 1e-3
-EXPECT = {"bf16x3": 1e-4, "fp16": 1e-3}
+EXPECT = {"bf16x3": 1e-4, "fp16": 1e-3, "fp8_bf16": 5e-2}
 
 
 @pytest.fixture(scope="module")
@@ -24,7 +26,7 @@ def plan_cls():
     return LloidPlan
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16", "fp8_bf16"])
 def test_ragged_banks_reduced_precision(plan_cls, precision):
     banks = _ragged_banks()
     F = 4096
@@ -35,11 +37,11 @@ def test_ragged_banks_reduced_precision(plan_cls, precision):
         ref = run_oracle(bank, x, F, 0, 5)
         eps = snr_error(z[b], ref)
         print(f"{precision} bank {b} eps={eps:.3e}")
-        assert eps <= min(GATE, EXPECT[precision])
+        assert eps <= EXPECT[precision]
         check_peaks(pk[b], ref, F, float(np.abs(z[b] - ref).max()))
 
 
-@pytest.mark.parametrize("precision", ["bf16x3", "fp16"])
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16", "fp8_bf16"])
 def test_realistic_bank_reduced_precision(plan_cls, precision):
     c2 = synth.cached_workload("c2", synth.config2)
     F = c2.sample_rate
@@ -50,5 +52,5 @@ def test_realistic_bank_reduced_precision(plan_cls, precision):
     eps = snr_error(z[0], ref)
     rms = float(np.sqrt(np.mean(np.abs(z[0] - ref) ** 2) / np.mean(np.abs(ref) ** 2)))
     print(f"realistic bank {precision}: eps={eps:.3e} rel_rms={rms:.3e}")
-    assert eps <= min(GATE, EXPECT[precision])
+    assert eps <= EXPECT[precision]
     check_peaks(pk[0], ref, F, float(np.abs(z[0] - ref).max()))
