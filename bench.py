@@ -12,6 +12,9 @@ Workloads (synthetic, seeded; see synth/):
   realistic  1 detector, 1024 chirp templates, 5 rates 4096..256 Hz,
              L = 40/60/80/100/120
   plain      1 detector, 64 templates, 2 rates (2048/512 Hz)
+  largest    2 detectors, 800 uneven sub-banks (~474k templates, 3-6 rates
+             4096..128 Hz, filters 0.5-128 s, N up to 97k), 4096 Hz; meant
+             for --precision fp8_bf16
 
 The default precision is bf16x3 (BF16 operands, both sides split, FP32
 accumulation); --compare fp32 also times the plain FP32 path on the same
@@ -40,6 +43,9 @@ def log(msg: str) -> None:
 
 def workload(name: str):
     import synth
+    if name == "largest":
+        # ~11 GB of float64 bank: generated in memory each run, not cached
+        return synth.config5(progress=log)
     if name == "batched":
         return synth.cached_workload("c3", synth.config3)
     if name == "realistic":
@@ -130,11 +136,12 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="batched", choices=["batched", "realistic", "plain"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "realistic", "plain", "largest"])
     ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
     ap.add_argument("--compare", default="fp32", help="also time this precision ('' to skip)")
     ap.add_argument("--graph", type=int, default=1, help="replay one HIP graph per stride")
     ap.add_argument("--peaks-only", action="store_true")
+    ap.add_argument("--autotune", type=int, default=1, help="tune the tiling options before timing")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -145,7 +152,7 @@ def main() -> int:
         print(json.dumps({"error": "this build runs on one GPU: the filtering path has no multi-GPU "
                                    "form; run with --gpus 1"}))
         return 2
-    big = args.workload == "batched"
+    big = args.workload in ("batched", "largest")
     steps = args.steps if args.steps is not None else (32 if big else 2048)
     warmup = args.warmup if args.warmup is not None else (8 if big else 64)
 
@@ -174,8 +181,16 @@ def main() -> int:
     write = not args.peaks_only
     kf = kernel_flops(w)
 
+    tiling = {}
+
     def run(precision: str, profile: bool):
         plan = LloidPlan(w.banks, F, ND, precision)
+        if args.autotune:
+            from paper_2511_04730_amd.autotune import autotune
+            best = autotune(plan, strides[:4], write_series=write, log=log)
+            tiling[precision] = {k: best[k] for k in ("corr_split", "corr_group", "mix_group")}
+        else:
+            tiling[precision] = {k: plan.option(k) for k in ("corr_split", "corr_group", "mix_group")}
         if args.graph and not profile:
             plan.set_graph(True)
         ms, prof = timed(plan, strides, warmup, steps, write, profile)
@@ -210,7 +225,7 @@ def main() -> int:
         if not args.no_cpu_baseline:
             _, cerr, _ = parity_and_baseline(cplan, w, x, strides, k_par, min(args.cpu_seconds, 5.0))
         compare = {"precision": args.compare, "value": cval, "ms_per_step": cms / steps,
-                   "snr_err": cerr, "speedup": value / cval}
+                   "snr_err": cerr, "speedup": value / cval, "tiling": tiling.get(args.compare)}
         log(f"{args.compare}: {steps} strides in {cms:.2f} ms")
         cplan.close()
 
@@ -221,7 +236,7 @@ def main() -> int:
         "config": {"workload": w.name, "banks": len(w.banks), "templates": w.n_templates, "detectors": ND,
                    "rates_hz": sorted({s.rate for b in w.banks for s in b.slices}, reverse=True),
                    "precision": args.precision, "series_written": write, "graph": bool(args.graph),
-                   "stride_s": 1, "flops_per_stride": flops_per_stride},
+                   "stride_s": 1, "flops_per_stride": flops_per_stride, "tiling": tiling.get(args.precision)},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": None},
         "kernel_ms": kernel_ms,

@@ -140,7 +140,8 @@ typedef enum {
     LLOID_Q_N_SLICES = 8,            /* slices over all banks                     */
     LLOID_Q_SLICE_LOOKAHEAD = 9,     /* index = global slice: look-ahead samples  */
     LLOID_Q_FLOPS_PER_STRIDE = 10,   /* algorithmic flops of one stride           */
-    LLOID_Q_DEVICE_BYTES = 11        /* device memory the plan holds              */
+    LLOID_Q_DEVICE_BYTES = 11,       /* device memory the plan holds              */
+    LLOID_Q_OPTION = 12              /* index = lloid_option: its current value   */
 } lloid_query;
 
 lloid_status lloid_plan_query(const lloid_plan *plan, int32_t what, int32_t index, int64_t *value);
@@ -223,7 +224,19 @@ lloid_status lloid_set_slice(lloid_plan *plan, int32_t slice, const double *U_de
  * LLOID_E_STATE if a Gram matrix is not positive definite.  Synchronises. */
 lloid_status lloid_orthonormalize(double *U_dev, int32_t L, int32_t N, double *W_dev, int32_t rows, void *stream);
 
-/* Plan options (lloid_set_option).
+/* Plan options (lloid_set_option; current values via lloid_plan_query with
+ * LLOID_Q_OPTION).  The three tiling options change only how the work is cut
+ * into work groups, never what is computed; results stay deterministic for a
+ * given setting, but the correlation split changes the FP32 summation order.
+ * Setting one of them synchronises the device and drops a captured graph.
+ *   LLOID_OPT_CORR_SPLIT  taps per correlation work item (multiple of 64,
+ *                    64..65536; default chosen at plan time: the longest
+ *                    power of two from 8192 down to 512 that still yields
+ *                    2048 items).  The partial planes are reallocated.
+ *   LLOID_OPT_CORR_GROUP  consecutive correlation items kept on one XCD
+ *                    (0..64; 0 = dispatch order; default 16).
+ *   LLOID_OPT_MIX_GROUP   consecutive mixing items kept on one XCD
+ *                    (0..256; 0 = dispatch order; default 32).
  *   LLOID_OPT_GRAPH  1: lloid_push_stride copies the strain into a
  *                    plan-owned staging buffer on the call's stream and then
  *                    replays one captured HIP graph of the stride's kernels
@@ -234,8 +247,14 @@ lloid_status lloid_orthonormalize(double *U_dev, int32_t L, int32_t N, double *W
  *                    0 (default): the kernels are launched one by one.
  *                    While profiling is enabled, kernels are launched one by
  *                    one regardless.
- * Errors: LLOID_E_ARG (unknown option or value), LLOID_E_HIP. */
-typedef enum { LLOID_OPT_GRAPH = 0 } lloid_option;
+ * Errors: LLOID_E_ARG (unknown option or value), LLOID_E_HIP, LLOID_E_NOMEM
+ * (reallocating the partial planes failed; the plan must then be destroyed). */
+typedef enum {
+    LLOID_OPT_GRAPH = 0,
+    LLOID_OPT_CORR_SPLIT = 1,
+    LLOID_OPT_CORR_GROUP = 2,
+    LLOID_OPT_MIX_GROUP = 3
+} lloid_option;
 lloid_status lloid_set_option(lloid_plan *plan, int32_t option, int64_t value);
 
 /* Per-kernel timing of lloid_push_stride with HIP events recorded on the

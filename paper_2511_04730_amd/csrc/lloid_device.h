@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "lloid_internal.h"
+
 namespace lloid {
 
 // a mod m in [0, m) for negative a too
@@ -20,6 +22,17 @@ struct PeakCand {
 
 __device__ __forceinline__ bool better(float p2, int idx, float bp2, int bidx) {
     return p2 > bp2 || (p2 == bp2 && idx < bidx);
+}
+
+// Work item of this work group when `group` consecutive items are to share
+// one XCD (and its L2): the dispatcher deals work groups to the XCDs in turn,
+// so group b runs on XCD b mod kXcds.  group <= 0 keeps the launch order.
+// The grid is xcd_grid(n, group) long; items >= n exit at once.
+__device__ __forceinline__ int xcd_item(int group) {
+    const int b = blockIdx.x;
+    if (group <= 0) return b;
+    const int x = b % kXcds, k = b / kXcds;
+    return ((k / group) * kXcds + x) * group + k % group;
 }
 
 }  // namespace lloid

@@ -19,6 +19,14 @@ constexpr int kMixTM = 32;            // mixing tile: real rows (16 templates)
 constexpr int kMixTN = 256;           // mixing tile: top-rate samples
 constexpr int kUpTaps = 17;           // 2 N_up + 1 taps per polyphase branch
 constexpr int kMaxLdsBytes = 96 * 1024;   // dynamic LDS per work group we allow (160 KB on gfx950)
+constexpr int kXcds = 8;              // accelerator complex dies of the MI355X
+
+// grid length for xcd_item(): whole rounds of kXcds groups
+inline int xcd_grid(int n_items, int group) {
+    if (group <= 0) return n_items;
+    const int round = kXcds * group;
+    return (n_items + round - 1) / round * round;
+}
 
 // -------------------------------------------------------------- work items
 // Basis correlation (Sec. II.C.2 "Filtering and reconstruction"):
@@ -107,12 +115,12 @@ struct LaunchCtx {
 hipError_t launch_ingest(const LaunchCtx &, const float *strain, int64_t src_det_stride, uint32_t gap_mask,
                          float *xring, int64_t ring_det_stride, int32_t cap, int32_t F, int32_t n_det);
 hipError_t launch_down(const LaunchCtx &, const DownItem *items, int32_t n_items, int32_t max_lds_floats);
-hipError_t launch_corr(const LaunchCtx &, int precision, const CorrItem *items, int32_t n_items);
+hipError_t launch_corr(const LaunchCtx &, int precision, const CorrItem *items, int32_t n_items, int32_t group);
 hipError_t launch_reduce(const LaunchCtx &, const ReduceItem *items, int32_t n_items, int32_t max_rows);
 hipError_t launch_mix(const LaunchCtx &, int precision, const MixItem *items, int32_t n_items,
                       const MixBank *banks, const MixSlice *slices, const float *uptaps,
                       float *series, PartialPeak *partials, int32_t F, int32_t n_det,
-                      int32_t S, int32_t SW, int32_t nup);
+                      int32_t S, int32_t SW, int32_t nup, int32_t group);
 hipError_t launch_peaks(const LaunchCtx &, const PeakItem *items, int32_t n_items,
                         const PartialPeak *partials, lloid_peak *peaks, float threshold,
                         int64_t *stride_ctr_advance);

@@ -100,14 +100,16 @@ constexpr int kTKF = 32;             // taps per LDS stage
 constexpr int kUS = kTKF + 2;
 
 template <int MBMAX>
-__global__ __launch_bounds__(256) void corr_f32_kernel(const CorrItem *__restrict__ items,
-                                                       const int64_t *__restrict__ stride_ctr) {
+__global__ __launch_bounds__(256) void corr_f32_kernel(const CorrItem *__restrict__ items, int32_t n_items,
+                                                       int32_t group, const int64_t *__restrict__ stride_ctr) {
     // double-buffered: the next stage's tiles are loaded into registers while
     // the current stage's MFMAs run from LDS
     __shared__ float Us[2][MBMAX * 16 * kUS];
     __shared__ float ds[2][kCorrTQ + kTKF];
     constexpr int PER = (MBMAX * 16 * (kTKF / 2) + 255) / 256;
-    const CorrItem it = items[blockIdx.x];
+    const int item = xcd_item(group);
+    if (item >= n_items) return;
+    const CorrItem it = items[item];
     const int64_t kstr = *stride_ctr;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -191,8 +193,8 @@ __global__ __launch_bounds__(256) void corr_f32_kernel(const CorrItem *__restric
 //   SPLIT_U (bf16x3): U_hi d_lo + U_lo d_hi + U_hi d_hi
 //   otherwise (fp16): U d_lo + U d_hi
 template <typename T, typename T8, bool SPLIT_U>
-__global__ __launch_bounds__(256) void corr16_kernel(const CorrItem *__restrict__ items,
-                                                     const int64_t *__restrict__ stride_ctr) {
+__global__ __launch_bounds__(256) void corr16_kernel(const CorrItem *__restrict__ items, int32_t n_items,
+                                                     int32_t group, const int64_t *__restrict__ stride_ctr) {
     constexpr int TK = 64;
     constexpr int US = TK + 8;
     constexpr int MBMAX = kMaxBasis / 16;
@@ -201,7 +203,9 @@ __global__ __launch_bounds__(256) void corr16_kernel(const CorrItem *__restrict_
     __shared__ __attribute__((aligned(16))) T Ul[SPLIT_U ? MBMAX * 16 * US : 8];
     __shared__ __attribute__((aligned(16))) T Dh[8 * DL];
     __shared__ __attribute__((aligned(16))) T Dl[8 * DL];
-    const CorrItem it = items[blockIdx.x];
+    const int item = xcd_item(group);
+    if (item >= n_items) return;
+    const CorrItem it = items[item];
     const int64_t kstr = *stride_ctr;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -309,8 +313,8 @@ __device__ __forceinline__ uint32_t fp8_byte(float v) {
 }
 __device__ __forceinline__ float fp8_value(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
 
-__global__ __launch_bounds__(256) void corr8_kernel(const CorrItem *__restrict__ items,
-                                                    const int64_t *__restrict__ stride_ctr) {
+__global__ __launch_bounds__(256) void corr8_kernel(const CorrItem *__restrict__ items, int32_t n_items,
+                                                    int32_t group, const int64_t *__restrict__ stride_ctr) {
     constexpr int TK = 64;
     constexpr int US = TK + 16;            // bytes per basis row in LDS
     constexpr int MBMAX = kMaxBasis / 16;
@@ -318,7 +322,9 @@ __global__ __launch_bounds__(256) void corr8_kernel(const CorrItem *__restrict__
     __shared__ __attribute__((aligned(16))) uint8_t U8[MBMAX * 16 * US];
     __shared__ __attribute__((aligned(16))) uint8_t Dh[8 * DL];
     __shared__ __attribute__((aligned(16))) uint8_t Dl[8 * DL];
-    const CorrItem it = items[blockIdx.x];
+    const int item = xcd_item(group);
+    if (item >= n_items) return;
+    const CorrItem it = items[item];
     const int64_t kstr = *stride_ctr;
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
@@ -434,18 +440,20 @@ hipError_t launch_convert_fp8_rows(hipStream_t st, const double *src, int32_t ro
     return hipGetLastError();
 }
 
-hipError_t launch_corr_reduced(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items) {
+hipError_t launch_corr_reduced(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items,
+                               int32_t group) {
+    const dim3 grid(xcd_grid(n_items, group));
     switch (precision) {
         case LLOID_FP8_BF16:
-            hipLaunchKernelGGL(corr8_kernel, dim3(n_items), dim3(256), 0, ctx.stream, items, ctx.stride_ctr);
+            hipLaunchKernelGGL(corr8_kernel, grid, dim3(256), 0, ctx.stream, items, n_items, group, ctx.stride_ctr);
             break;
         case LLOID_BF16X3:
-            hipLaunchKernelGGL((corr16_kernel<__bf16, bf16x8, true>), dim3(n_items), dim3(256), 0, ctx.stream, items,
-                               ctx.stride_ctr);
+            hipLaunchKernelGGL((corr16_kernel<__bf16, bf16x8, true>), grid, dim3(256), 0, ctx.stream, items, n_items,
+                               group, ctx.stride_ctr);
             break;
         case LLOID_FP16:
-            hipLaunchKernelGGL((corr16_kernel<_Float16, halfx8, false>), dim3(n_items), dim3(256), 0, ctx.stream,
-                               items, ctx.stride_ctr);
+            hipLaunchKernelGGL((corr16_kernel<_Float16, halfx8, false>), grid, dim3(256), 0, ctx.stream, items,
+                               n_items, group, ctx.stride_ctr);
             break;
         default:
             return hipErrorNotSupported;
@@ -453,14 +461,14 @@ hipError_t launch_corr_reduced(const LaunchCtx &ctx, int precision, const CorrIt
     return hipGetLastError();
 }
 
-hipError_t launch_corr(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items) {
+hipError_t launch_corr(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items, int32_t group) {
     if (n_items == 0) return hipSuccess;
-    if (precision != LLOID_FP32) return launch_corr_reduced(ctx, precision, items, n_items);
-    hipLaunchKernelGGL(corr_f32_kernel<kMaxBasis / 16>, dim3(n_items), dim3(256), 0, ctx.stream, items, ctx.stride_ctr);
+    if (precision != LLOID_FP32) return launch_corr_reduced(ctx, precision, items, n_items, group);
+    hipLaunchKernelGGL(corr_f32_kernel<kMaxBasis / 16>, dim3(xcd_grid(n_items, group)), dim3(256), 0, ctx.stream,
+                       items, n_items, group, ctx.stride_ctr);
     return hipGetLastError();
 }
 
-// ------------------------------------------------------ split-K reduction
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceItem *__restrict__ items,
                                                      const int64_t *__restrict__ stride_ctr) {
     const ReduceItem it = items[blockIdx.x];

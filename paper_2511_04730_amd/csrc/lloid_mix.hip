@@ -189,7 +189,8 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ it
                                                   const MixSlice *__restrict__ slices,
                                                   const float *__restrict__ uptaps, float *__restrict__ series,
                                                   PartialPeak *__restrict__ partials, int32_t F, int32_t S,
-                                                  int32_t nup, const int64_t *__restrict__ stride_ctr) {
+                                                  int32_t nup, int32_t n_items, int32_t group,
+                                                  const int64_t *__restrict__ stride_ctr) {
     extern __shared__ float sm[];
     constexpr int TM = kMixTM;
     float *bufA = sm;
@@ -198,7 +199,9 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ it
     float *Wc = Ys + Op::CH * kSY;
     __shared__ PeakCand wbest[4][TM / 2];
 
-    const MixItem it = items[blockIdx.x];
+    const int item = xcd_item(group);
+    if (item >= n_items) return;
+    const MixItem it = items[item];
     const MixBank &B = banks[it.bank];
     const int64_t kstr = *stride_ctr;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -372,25 +375,27 @@ hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes) {
 
 hipError_t launch_mix(const LaunchCtx &ctx, int precision, const MixItem *items, int32_t n_items,
                       const MixBank *banks, const MixSlice *slices, const float *uptaps, float *series,
-                      PartialPeak *partials, int32_t F, int32_t n_det, int32_t S, int32_t SW, int32_t nup) {
+                      PartialPeak *partials, int32_t F, int32_t n_det, int32_t S, int32_t SW, int32_t nup,
+                      int32_t group) {
     (void)n_det;
     (void)SW;
     if (n_items == 0) return hipSuccess;
     const size_t lds = mix_lds(precision, S);
+    const dim3 grid(xcd_grid(n_items, group));
     switch (precision) {
         case LLOID_FP32:
-            hipLaunchKernelGGL(mix_kernel<MixF32>, dim3(n_items), dim3(256), lds, ctx.stream, items, banks, slices,
-                               uptaps, series, partials, F, S, nup, ctx.stride_ctr);
+            hipLaunchKernelGGL(mix_kernel<MixF32>, grid, dim3(256), lds, ctx.stream, items, banks, slices,
+                               uptaps, series, partials, F, S, nup, n_items, group, ctx.stride_ctr);
             break;
         case LLOID_BF16X3:
         case LLOID_FP8_BF16:
-            hipLaunchKernelGGL((mix_kernel<Mix16<__bf16, bf16x8, true>>), dim3(n_items), dim3(256), lds, ctx.stream,
-                               items, banks, slices, uptaps, series, partials, F, S, nup, ctx.stride_ctr);
+            hipLaunchKernelGGL((mix_kernel<Mix16<__bf16, bf16x8, true>>), grid, dim3(256), lds, ctx.stream,
+                               items, banks, slices, uptaps, series, partials, F, S, nup, n_items, group, ctx.stride_ctr);
             break;
         case LLOID_FP16:
-            hipLaunchKernelGGL((mix_kernel<Mix16<_Float16, halfx8, false>>), dim3(n_items), dim3(256), lds,
+            hipLaunchKernelGGL((mix_kernel<Mix16<_Float16, halfx8, false>>), grid, dim3(256), lds,
                                ctx.stream, items, banks, slices, uptaps, series, partials, F, S, nup,
-                               ctx.stride_ctr);
+                               n_items, group, ctx.stride_ctr);
             break;
         default:
             return hipErrorNotSupported;

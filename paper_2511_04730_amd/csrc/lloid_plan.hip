@@ -119,6 +119,8 @@ struct lloid_plan {
     uint32_t g_gap = 0;
     double flops = 0.0;
     int ksplit = kCorrSplitK;      // taps per correlation work item
+    int corr_group = 16;           // consecutive correlation items per XCD
+    int mix_group = 32;            // consecutive mixing items per XCD
 
     // per-kernel event timing (lloid_profile_*)
     bool profiling = false;
@@ -184,6 +186,66 @@ template <typename T>
 lloid_status upload(lloid_plan *P, T **dst, const std::vector<T> &v, hipStream_t st) {
     ST_OK(P->alloc(dst, v.size(), false));
     if (!v.empty()) HIP_OK(hipMemcpyAsync(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return LLOID_OK;
+}
+
+// Correlation work items and their split-K reduction for the current tap
+// split P->ksplit: one item per (slice, detector, tap split, 64-column
+// tile), largest first; the partial planes are (re)allocated to match.
+lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
+    const int ND = P->n_det;
+    P->release(P->d_corr);
+    P->release(P->d_reduce);
+    P->d_corr = nullptr;
+    P->d_reduce = nullptr;
+    std::vector<CorrItem> items;
+    std::vector<ReduceItem> red;
+    P->reduce_rows = 0;
+    for (auto &s : P->slices) {
+        const Ring &r = P->rings[s.D];
+        const int f = s.rate;
+        s.nsplit = (s.Npad + P->ksplit - 1) / P->ksplit;
+        P->release(s.part);
+        s.part_det = (int64_t)s.nsplit * s.Lpad * f;
+        ST_OK(P->alloc(&s.part, (size_t)ND * s.part_det, false));
+        for (int det = 0; det < ND; ++det) {
+            for (int sp = 0; sp < s.nsplit; ++sp) {
+                const int k0 = sp * P->ksplit;
+                const int klen = std::min(P->ksplit, s.Npad - k0);
+                for (int c0 = 0; c0 < f; c0 += kCorrTQ) {
+                    CorrItem it{};
+                    it.U = s.U32;
+                    it.Uhi = s.Uhi;
+                    it.Ulo = s.Ulo;
+                    it.ring = r.base + det * r.det_stride;
+                    it.part = s.part + det * s.part_det + (int64_t)sp * s.Lpad * f;
+                    it.uscale = s.uscale;
+                    it.off = (int64_t)s.la - s.delay - (s.N - 1);
+                    it.Npad = s.Npad;
+                    it.Lpad = s.Lpad;
+                    it.cap = r.cap;
+                    it.f = f;
+                    it.col0 = c0;
+                    it.ncols = std::min(kCorrTQ, f - c0);
+                    it.k0 = k0;
+                    it.klen = klen;
+                    it.mb = s.Lpad / 16;
+                    items.push_back(it);
+                }
+            }
+            red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L, s.Lpad, f,
+                                     s.capY, s.la});
+            P->reduce_rows = std::max(P->reduce_rows, s.L);
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const CorrItem &a, const CorrItem &b) {
+        return (int64_t)a.klen * a.mb * a.ncols > (int64_t)b.klen * b.mb * b.ncols;
+    });
+    P->n_corr = (int)items.size();
+    P->n_reduce = (int)red.size();
+    ST_OK(upload(P, &P->d_corr, items, st));
+    ST_OK(upload(P, &P->d_reduce, red, st));
+    HIP_OK(hipStreamSynchronize(st));
     return LLOID_OK;
 }
 
@@ -328,7 +390,6 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                 break;
             }
         }
-        for (auto &s : P->slices) s.nsplit = (s.Npad + P->ksplit - 1) / P->ksplit;
     }
     P->n_peaks = peak_off;
 
@@ -439,8 +500,6 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
     for (auto &s : P->slices) {
         s.ydet = (int64_t)s.Lpad * 2 * s.capY;
         ST_OK(P->alloc(&s.yring, (size_t)ND * s.ydet));
-        s.part_det = (int64_t)s.nsplit * s.Lpad * s.rate;
-        ST_OK(P->alloc(&s.part, (size_t)ND * s.part_det, false));
     }
 
     // ---------------------------------------------------------- resampler taps
@@ -497,52 +556,9 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         P->n_downitems = (int)items.size();
         ST_OK(upload(P, &P->d_down, items, st));
     }
-    {
-        std::vector<CorrItem> items;
-        std::vector<ReduceItem> red;
-        for (auto &s : P->slices) {
-            const Ring &r = P->rings[s.D];
-            const int f = s.rate;
-            for (int det = 0; det < ND; ++det) {
-                for (int sp = 0; sp < s.nsplit; ++sp) {
-                    const int k0 = sp * P->ksplit;
-                    const int klen = std::min(P->ksplit, s.Npad - k0);
-                    for (int c0 = 0; c0 < f; c0 += kCorrTQ) {
-                        CorrItem it{};
-                        it.U = s.U32;
-                        it.Uhi = s.Uhi;
-                        it.Ulo = s.Ulo;
-                        it.ring = r.base + det * r.det_stride;
-                        it.part = s.part + det * s.part_det + (int64_t)sp * s.Lpad * f;
-                        it.uscale = s.uscale;
-                        it.off = (int64_t)s.la - s.delay - (s.N - 1);
-                        it.Npad = s.Npad;
-                        it.Lpad = s.Lpad;
-                        it.cap = r.cap;
-                        it.f = f;
-                        it.col0 = c0;
-                        it.ncols = std::min(kCorrTQ, f - c0);
-                        it.k0 = k0;
-                        it.klen = klen;
-                        it.mb = s.Lpad / 16;
-                        items.push_back(it);
-                    }
-                }
-                red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L, s.Lpad, f,
-                                         s.capY, s.la});
-                P->reduce_rows = std::max(P->reduce_rows, s.L);
-            }
-            // algorithmic flops: correlation and mixing contractions
-            P->flops += (double)ND * (2.0 * s.L * s.N * f + 2.0 * 2.0 * P->banks[s.bank].M * s.L * f);
-        }
-        std::stable_sort(items.begin(), items.end(), [](const CorrItem &a, const CorrItem &b) {
-            return (int64_t)a.klen * a.mb * a.ncols > (int64_t)b.klen * b.mb * b.ncols;
-        });
-        P->n_corr = (int)items.size();
-        P->n_reduce = (int)red.size();
-        ST_OK(upload(P, &P->d_corr, items, st));
-        ST_OK(upload(P, &P->d_reduce, red, st));
-    }
+    ST_OK(build_corr_tables(P, st));
+    for (auto &s : P->slices)   // algorithmic flops: correlation and mixing contractions
+        P->flops += (double)ND * (2.0 * s.L * s.N * s.rate + 2.0 * 2.0 * P->banks[s.bank].M * s.L * s.rate);
     {
         std::vector<MixBank> mb;
         std::vector<MixSlice> ms;
@@ -588,9 +604,11 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
             m.part_off = pb.part_off;
             m.n_ttiles = n_ttiles;
             mb.push_back(m);
+            // row tiles innermost: the work groups that run together on one
+            // XCD read the same basis-output window from its L2
             for (int det = 0; det < ND; ++det) {
-                for (int r0 = 0; r0 < pb.rows_pad; r0 += kMixTM)
-                    for (int t0 = 0; t0 < F; t0 += kMixTN) items.push_back(MixItem{b, det, r0, t0});
+                for (int t0 = 0; t0 < F; t0 += kMixTN)
+                    for (int r0 = 0; r0 < pb.rows_pad; r0 += kMixTM) items.push_back(MixItem{b, det, r0, t0});
                 pk.push_back(PeakItem{pb.part_off + (int64_t)det * pb.M * n_ttiles, pb.peak_off + (int64_t)det * pb.M,
                                       pb.M, n_ttiles});
             }
@@ -648,6 +666,15 @@ lloid_status lloid_plan_query(const lloid_plan *P, int32_t what, int32_t index, 
         case LLOID_Q_FLOPS_PER_STRIDE: *value = (int64_t)P->flops; return LLOID_OK;
         case LLOID_Q_DEVICE_BYTES: *value = (int64_t)P->device_bytes; return LLOID_OK;
         default: break;
+    }
+    if (what == LLOID_Q_OPTION) {
+        switch (index) {
+            case LLOID_OPT_GRAPH: *value = P->use_graph ? 1 : 0; return LLOID_OK;
+            case LLOID_OPT_CORR_SPLIT: *value = P->ksplit; return LLOID_OK;
+            case LLOID_OPT_CORR_GROUP: *value = P->corr_group; return LLOID_OK;
+            case LLOID_OPT_MIX_GROUP: *value = P->mix_group; return LLOID_OK;
+            default: return LLOID_E_ARG;
+        }
     }
     if (what == LLOID_Q_SLICE_LOOKAHEAD) {
         if (index < 0 || index >= (int)P->slices.size()) return LLOID_E_ARG;
@@ -709,7 +736,33 @@ lloid_status lloid_set_option(lloid_plan *P, int32_t option, int64_t value) {
         P->use_graph = value != 0;
         return LLOID_OK;
     }
-    return LLOID_E_ARG;
+    switch (option) {
+        case LLOID_OPT_CORR_SPLIT:
+            if (value < kCorrTK || value > 65536 || value % kCorrTK) return LLOID_E_ARG;
+            break;
+        case LLOID_OPT_CORR_GROUP:
+            if (value < 0 || value > 64) return LLOID_E_ARG;
+            break;
+        case LLOID_OPT_MIX_GROUP:
+            if (value < 0 || value > 256) return LLOID_E_ARG;
+            break;
+        default:
+            return LLOID_E_ARG;
+    }
+    // the captured graph holds the old work tables and launch shapes
+    HIP_OK(hipDeviceSynchronize());
+    if (P->gexec) HIP_OK(hipGraphExecDestroy(P->gexec));
+    if (P->graph) HIP_OK(hipGraphDestroy(P->graph));
+    P->gexec = nullptr;
+    P->graph = nullptr;
+    if (option == LLOID_OPT_CORR_SPLIT) {
+        if (P->ksplit == (int)value) return LLOID_OK;
+        P->ksplit = (int)value;
+        return build_corr_tables(P, nullptr);
+    }
+    if (option == LLOID_OPT_CORR_GROUP) P->corr_group = (int)value;
+    if (option == LLOID_OPT_MIX_GROUP) P->mix_group = (int)value;
+    return LLOID_OK;
 }
 
 static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *strain, uint32_t gap_mask,
@@ -724,14 +777,14 @@ static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *s
     HIP_OK(launch_down(ctx, P->d_down, P->n_downitems, P->down_lds));
     HIP_OK(P->mark(LLOID_K_DOWN, st, false));
     HIP_OK(P->mark(LLOID_K_CORR, st, true));
-    HIP_OK(launch_corr(ctx, P->precision, P->d_corr, P->n_corr));
+    HIP_OK(launch_corr(ctx, P->precision, P->d_corr, P->n_corr, P->corr_group));
     HIP_OK(P->mark(LLOID_K_CORR, st, false));
     HIP_OK(P->mark(LLOID_K_REDUCE, st, true));
     HIP_OK(launch_reduce(ctx, P->d_reduce, P->n_reduce, P->reduce_rows));
     HIP_OK(P->mark(LLOID_K_REDUCE, st, false));
     HIP_OK(P->mark(LLOID_K_MIX, st, true));
     HIP_OK(launch_mix(ctx, P->precision, P->d_mix, P->n_mix, P->d_mbanks, P->d_mslices, P->d_uptaps, snr,
-                      P->d_partials, P->F, P->n_det, P->mixS, P->mixSW, P->nup));
+                      P->d_partials, P->F, P->n_det, P->mixS, P->mixSW, P->nup, P->mix_group));
     HIP_OK(P->mark(LLOID_K_MIX, st, false));
     HIP_OK(P->mark(LLOID_K_PEAKS, st, true));
     HIP_OK(launch_peaks(ctx, P->d_peakitems, P->n_peakitems, P->d_partials, peaks, P->cfg.snr_threshold,
@@ -1097,7 +1150,7 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
                     HIP_OK(hipMemcpyAsync(d_items, items.data(), sizeof(CorrItem) * items.size(),
                                           hipMemcpyHostToDevice, st));
                     LaunchCtx ctx{st, zero};
-                    HIP_OK(launch_corr(ctx, LLOID_FP32, d_items, (int32_t)items.size()));
+                    HIP_OK(launch_corr(ctx, LLOID_FP32, d_items, (int32_t)items.size(), 0));
                     HIP_OK(launch_sum_parts(st, part, (int32_t)nsu, (int64_t)s.Lpad * s.N, s.L, s.N, s.N,
                                             dU + offU[i], s.N, 1.0f, d > 0));
                     HIP_OK(hipStreamSynchronize(st));   // items buffer reused

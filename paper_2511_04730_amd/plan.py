@@ -77,7 +77,17 @@ class LloidPlan:
 
     def set_graph(self, enable: bool = True) -> None:
         """Replay one captured HIP graph per stride (LLOID_OPT_GRAPH)."""
-        L.check(self.lib.lloid_set_option(self.handle, 0, 1 if enable else 0), "lloid_set_option")
+        self.set_option("graph", 1 if enable else 0)
+
+    def set_option(self, name: str, value: int) -> None:
+        """lloid_set_option by name: graph, corr_split, corr_group, mix_group."""
+        L.check(self.lib.lloid_set_option(self.handle, L.OPTIONS[name], int(value)), "lloid_set_option")
+
+    def option(self, name: str) -> int:
+        return self.query(L.Q_OPTION, L.OPTIONS[name])
+
+    def options(self) -> dict:
+        return {k: self.option(k) for k in L.OPTIONS}
 
     def query(self, what: int, index: int = 0) -> int:
         v = ctypes.c_int64()

@@ -403,10 +403,14 @@ def config4(duration_s: int = 64) -> Workload:
 
 
 def batched_banks(config: int, n_banks: int, n_rates_range, duration_range,
-                  dtype=np.float64) -> List[Bank]:
+                  dtype=np.float64, progress=None) -> List[Bank]:
     g = rng_for(config, PURPOSE_STRUCT)
-    return [random_subbank(g, 4096, n_rates_range, (200, 1000), duration_range, (20, 150), dtype)
-            for _ in range(n_banks)]
+    banks = []
+    for i in range(n_banks):
+        banks.append(random_subbank(g, 4096, n_rates_range, (200, 1000), duration_range, (20, 150), dtype))
+        if progress is not None and (i + 1) % 100 == 0:
+            progress(f"generated {i + 1} of {n_banks} banks")
+    return banks
 
 
 def config3(n_banks: int = 200, duration_s: int = 256) -> Workload:
@@ -416,11 +420,11 @@ def config3(n_banks: int = 200, duration_s: int = 256) -> Workload:
                     batched_banks(3, n_banks, (3, 7), (0.5, 64.0)))
 
 
-def config5(n_banks: int = 800, duration_s: int = 1024, dtype=np.float64) -> Workload:
+def config5(n_banks: int = 800, duration_s: int = 1024, dtype=np.float64, progress=None) -> Workload:
     """Largest single-GPU share: 2 detectors, 1024 s at 4096 Hz, 800 uneven
     sub-banks (up to 6 rates, lowest 128 Hz, filters up to 128 s)."""
     return Workload("batched-800banks-2det-4096Hz", 5, 4096, 2, duration_s,
-                    batched_banks(5, n_banks, (3, 6), (0.5, 128.0), dtype))
+                    batched_banks(5, n_banks, (3, 6), (0.5, 128.0), dtype, progress))
 
 
 CACHE_VERSION = 1
