@@ -47,11 +47,12 @@ struct CorrItem {
     int32_t pad_;
 };
 
-// Deterministic split-K reduction into the basis-output ring.
+// Deterministic split-K reduction of 64 new columns of one slice and
+// detector into its basis-output ring (time-major, see MixSlice).
 struct ReduceItem {
     const float *part;       // [nsplit][Lpad][f]
-    float *yring;            // [Lpad][2 capY] mirror ring
-    int32_t nsplit, L, Lpad, f, capY, la;
+    void *yring;             // ring of this detector
+    int32_t nsplit, L, Lpad, f, capY, la, c0, pad_;
 };
 
 // Decimation (Eq. (sinc) kernel, zero phase): d_D[m] = sum_t g[t] x[D m + t - c]
@@ -64,12 +65,18 @@ struct DownItem {
 };
 
 // Mixing + upsample-and-add (Sec. II.C.2 "Upsampling", "Combining", Sec. II.C.3).
+// Basis-output ring of a slice and detector: time-major mirror ring of
+// 2 capY rows (capY a power of two; position q at q mod capY and
+// q mod capY + capY), each row the Lpad basis outputs of one sample:
+//   FP32 form:   float [2 capY][Lpad]
+//   16-bit forms: T hi [2 capY][Lpad], then T lo [2 capY][Lpad]  (y = hi + lo)
+// Either way 4 bytes per element; ydet counts 4-byte elements.
 struct MixSlice {
-    const float *W;          // [2M][Lpad] fp32 normalised mixing rows
+    const float *W;          // [rows_pad][Lpad] fp32 normalised mixing rows
     const void *Whi;         // reduced precision
     const void *Wlo;
-    const float *Y;          // basis-output ring of detector 0 [Lpad][2 capY]
-    int64_t ydet;            // floats between detectors' rings
+    const void *Y;           // basis-output ring of detector 0
+    int64_t ydet;            // 4-byte elements between detectors' rings
     int32_t L, Lpad, capY, level;
 };
 
@@ -78,7 +85,9 @@ struct MixBank {
     int32_t nlev;            // levels 0..nlev-1 (0 = top rate)
     int32_t rate[kMaxLevels];
     int32_t P[kMaxLevels];       // decimation of the level w.r.t. the top rate
+    int32_t shP[kMaxLevels];     // log2 P
     int32_t p[kMaxLevels];       // p[j] = rate[j-1] / rate[j] (j >= 1)
+    int32_t shp[kMaxLevels];     // log2 p
     int32_t lo[kMaxLevels];      // window start of tile t0 = 0, local index
     int32_t n[kMaxLevels];       // window length
     int32_t up_off[kMaxLevels];  // offset of level j's sub-kernels in the tap table
@@ -116,7 +125,7 @@ hipError_t launch_ingest(const LaunchCtx &, const float *strain, int64_t src_det
                          float *xring, int64_t ring_det_stride, int32_t cap, int32_t F, int32_t n_det);
 hipError_t launch_down(const LaunchCtx &, const DownItem *items, int32_t n_items, int32_t max_lds_floats);
 hipError_t launch_corr(const LaunchCtx &, int precision, const CorrItem *items, int32_t n_items, int32_t group);
-hipError_t launch_reduce(const LaunchCtx &, const ReduceItem *items, int32_t n_items, int32_t max_rows);
+hipError_t launch_reduce(const LaunchCtx &, int precision, const ReduceItem *items, int32_t n_items);
 hipError_t launch_mix(const LaunchCtx &, int precision, const MixItem *items, int32_t n_items,
                       const MixBank *banks, const MixSlice *slices, const float *uptaps,
                       float *series, PartialPeak *partials, int32_t F, int32_t n_det,
@@ -130,6 +139,11 @@ inline size_t mix_lds_bytes(int precision, int S) { return mix_lds(precision, S)
 // FP8 e4m3 rows with one power-of-two scale per row (basis role of LLOID_FP8_BF16)
 hipError_t launch_convert_fp8_rows(hipStream_t, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
                                    uint8_t *dst, int32_t dst_ld, float *scale);
+
+// rows [0, rows) of a time-major basis-output ring, positions a .. a+len-1,
+// as float rows dst[r * dst_ld + dst_off + c]
+hipError_t launch_ring_gather(hipStream_t, int precision, const void *ring, int32_t Lpad, int32_t cap, int64_t a,
+                              int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off);
 
 // gradient and re-orthonormalisation (lloid_grad.hip)
 hipError_t launch_copy_window(hipStream_t, const float *ring, int64_t ring_ld, int32_t cap, int64_t a,

@@ -469,28 +469,122 @@ hipError_t launch_corr(const LaunchCtx &ctx, int precision, const CorrItem *item
     return hipGetLastError();
 }
 
+// Sum the split partials of 64 new columns in a fixed order (split 0
+// first), transpose through LDS and append them to the time-major ring:
+// one row of Lpad outputs per sample, rows L .. Lpad-1 zero.  16-bit forms
+// store y as hi = T(y) and lo = T(y - hi) in two planes.
+template <typename T>
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceItem *__restrict__ items,
                                                      const int64_t *__restrict__ stride_ctr) {
+    __shared__ float sm[kMaxBasis][65];
     const ReduceItem it = items[blockIdx.x];
-    const int l = blockIdx.y;
-    if (l >= it.L) return;
     const int64_t k = *stride_ctr;
-    const int64_t q0 = k * it.f + it.la;
+    const int ncols = min(64, it.f - it.c0);
     const int64_t plane = (int64_t)it.Lpad * it.f;
-    float *row = it.yring + (int64_t)l * 2 * it.capY;
-    for (int c = threadIdx.x; c < it.f; c += blockDim.x) {
+    for (int e = threadIdx.x; e < it.L * 64; e += 256) {
+        const int l = e >> 6, c = e & 63;
         float s = 0.0f;
-        const float *p = it.part + (int64_t)l * it.f + c;
-        for (int sp = 0; sp < it.nsplit; ++sp) s += p[sp * plane];
-        const int64_t pos = posmod(q0 + c, it.capY);
-        row[pos] = s;
-        row[pos + it.capY] = s;
+        if (c < ncols) {
+            const float *p = it.part + (int64_t)l * it.f + it.c0 + c;
+            for (int sp = 0; sp < it.nsplit; ++sp) s += p[sp * plane];
+        }
+        sm[l][c] = s;
+    }
+    __syncthreads();
+    const int64_t q0 = k * it.f + it.la + it.c0;
+    const int64_t mask = it.capY - 1;
+    constexpr int V = sizeof(T) == 4 ? 4 : 8;   // outputs per thread and row: 16 bytes
+    const int groups = it.Lpad / V;
+    for (int e = threadIdx.x; e < ncols * groups; e += 256) {
+        const int c = e / groups, l = (e % groups) * V;
+        const int64_t pos = (q0 + c) & mask;
+        if constexpr (sizeof(T) == 4) {
+            float4 v;
+            v.x = l + 0 < it.L ? sm[l + 0][c] : 0.0f;
+            v.y = l + 1 < it.L ? sm[l + 1][c] : 0.0f;
+            v.z = l + 2 < it.L ? sm[l + 2][c] : 0.0f;
+            v.w = l + 3 < it.L ? sm[l + 3][c] : 0.0f;
+            float *ring = static_cast<float *>(it.yring);
+            *reinterpret_cast<float4 *>(ring + pos * it.Lpad + l) = v;
+            *reinterpret_cast<float4 *>(ring + (pos + it.capY) * it.Lpad + l) = v;
+        } else {
+            typedef T T8 __attribute__((ext_vector_type(8)));
+            T8 h, lo;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float y = l + i < it.L ? sm[l + i][c] : 0.0f;
+                h[i] = (T)y;
+                lo[i] = (T)(y - (float)h[i]);
+            }
+            T *hi_plane = static_cast<T *>(it.yring);
+            T *lo_plane = hi_plane + 2LL * it.capY * it.Lpad;
+            *reinterpret_cast<T8 *>(hi_plane + pos * it.Lpad + l) = h;
+            *reinterpret_cast<T8 *>(hi_plane + (pos + it.capY) * it.Lpad + l) = h;
+            *reinterpret_cast<T8 *>(lo_plane + pos * it.Lpad + l) = lo;
+            *reinterpret_cast<T8 *>(lo_plane + (pos + it.capY) * it.Lpad + l) = lo;
+        }
     }
 }
 
-hipError_t launch_reduce(const LaunchCtx &ctx, const ReduceItem *items, int32_t n_items, int32_t max_rows) {
+hipError_t launch_reduce(const LaunchCtx &ctx, int precision, const ReduceItem *items, int32_t n_items) {
     if (n_items == 0) return hipSuccess;
-    hipLaunchKernelGGL(reduce_kernel, dim3(n_items, max_rows), dim3(256), 0, ctx.stream, items, ctx.stride_ctr);
+    switch (precision) {
+        case LLOID_FP32:
+            hipLaunchKernelGGL(reduce_kernel<float>, dim3(n_items), dim3(256), 0, ctx.stream, items, ctx.stride_ctr);
+            break;
+        case LLOID_BF16X3:
+        case LLOID_FP8_BF16:
+            hipLaunchKernelGGL(reduce_kernel<__bf16>, dim3(n_items), dim3(256), 0, ctx.stream, items,
+                               ctx.stride_ctr);
+            break;
+        case LLOID_FP16:
+            hipLaunchKernelGGL(reduce_kernel<_Float16>, dim3(n_items), dim3(256), 0, ctx.stream, items,
+                               ctx.stride_ctr);
+            break;
+        default:
+            return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+__global__ void ring_gather_kernel(const void *__restrict__ ring, int32_t Lpad, int32_t cap, int64_t a, int32_t len,
+                                   int32_t rows, float *__restrict__ dst, int64_t dst_ld, int64_t dst_off) {
+    const int r = blockIdx.y;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows || c >= len) return;
+    const int64_t p = posmod(a, cap) + c;   // mirror ring: p < 2 cap
+    float v;
+    if constexpr (sizeof(T) == 4) {
+        v = static_cast<const float *>(ring)[p * Lpad + r];
+    } else {
+        const T *hi = static_cast<const T *>(ring);
+        v = (float)hi[p * Lpad + r] + (float)hi[2LL * cap * Lpad + p * Lpad + r];
+    }
+    dst[r * dst_ld + dst_off + c] = v;
+}
+
+hipError_t launch_ring_gather(hipStream_t st, int precision, const void *ring, int32_t Lpad, int32_t cap, int64_t a,
+                              int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off) {
+    if (len <= 0 || rows <= 0) return hipSuccess;
+    const dim3 grid((len + 255) / 256, rows);
+    switch (precision) {
+        case LLOID_FP32:
+            hipLaunchKernelGGL(ring_gather_kernel<float>, grid, dim3(256), 0, st, ring, Lpad, cap, a, len, rows, dst,
+                               dst_ld, dst_off);
+            break;
+        case LLOID_BF16X3:
+        case LLOID_FP8_BF16:
+            hipLaunchKernelGGL(ring_gather_kernel<__bf16>, grid, dim3(256), 0, st, ring, Lpad, cap, a, len, rows, dst,
+                               dst_ld, dst_off);
+            break;
+        case LLOID_FP16:
+            hipLaunchKernelGGL(ring_gather_kernel<_Float16>, grid, dim3(256), 0, st, ring, Lpad, cap, a, len, rows,
+                               dst, dst_ld, dst_off);
+            break;
+        default:
+            return hipErrorNotSupported;
+    }
     return hipGetLastError();
 }
 

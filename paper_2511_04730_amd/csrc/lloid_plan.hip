@@ -29,7 +29,7 @@ using namespace lloid;
 
 namespace {
 
-constexpr uint64_t kStateMagic = 0x4c4c4f4944535431ull;   // "LLOIDST1"
+constexpr uint64_t kStateMagic = 0x4c4c4f4944535432ull;   // "LLOIDST2": time-major basis-output rings
 
 int ilog2(int v) {
     int r = 0;
@@ -233,8 +233,9 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
                     items.push_back(it);
                 }
             }
-            red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L, s.Lpad, f,
-                                     s.capY, s.la});
+            for (int c0 = 0; c0 < f; c0 += 64)
+                red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L, s.Lpad, f,
+                                         s.capY, s.la, c0, 0});
             P->reduce_rows = std::max(P->reduce_rows, s.L);
         }
     }
@@ -353,7 +354,9 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
             ps.delay = S.delay;
             ps.nsplit = (int)((ps.Npad + kCorrSplitK - 1) / kCorrSplitK);
             const int f = S.rate_hz;
-            ps.capY = f + 2 * ps.la + 16;
+            // power of two: the mixing takes ring positions with a mask
+            ps.capY = 1;
+            while (ps.capY < f + 2 * ps.la + 16) ps.capY *= 2;
             // pre-synchronisation: the newest sample the slice reads must be
             // available at the end of the stride
             const int64_t need = ps.la + (ps.D > 1 ? ndown : 0);
@@ -574,9 +577,11 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
             for (int j = 0; j < pb.nlev; ++j) {
                 m.rate[j] = pb.rates[j];
                 m.P[j] = F / pb.rates[j];
+                m.shP[j] = ilog2(m.P[j]);
                 if (j > 0) {
                     const int p = pb.rates[j - 1] / pb.rates[j];
                     m.p[j] = p;
+                    m.shp[j] = ilog2(p);
                     lo = floordiv(lo, p) - nup;
                     hi = floordiv(hi - 1, p) + nup + 1;
                     S = std::max<int>(S, (int)(hi - lo));
@@ -593,6 +598,7 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                 for (int id : pb.slices) {
                     PSlice &s = P->slices[id];
                     if (s.level != j) continue;
+                    if (m.n[j] > s.capY) return LLOID_E_UNSUPPORTED;   // a tile's window must fit the ring
                     ms.push_back(MixSlice{s.W32, s.Whi, s.Wlo, s.yring, s.ydet, s.L, s.Lpad, s.capY, s.level});
                     lvl_l[j] += s.Lpad;
                 }
@@ -780,7 +786,7 @@ static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *s
     HIP_OK(launch_corr(ctx, P->precision, P->d_corr, P->n_corr, P->corr_group));
     HIP_OK(P->mark(LLOID_K_CORR, st, false));
     HIP_OK(P->mark(LLOID_K_REDUCE, st, true));
-    HIP_OK(launch_reduce(ctx, P->d_reduce, P->n_reduce, P->reduce_rows));
+    HIP_OK(launch_reduce(ctx, P->precision, P->d_reduce, P->n_reduce));
     HIP_OK(P->mark(LLOID_K_REDUCE, st, false));
     HIP_OK(P->mark(LLOID_K_MIX, st, true));
     HIP_OK(launch_mix(ctx, P->precision, P->d_mix, P->n_mix, P->d_mbanks, P->d_mslices, P->d_uptaps, snr,
@@ -936,10 +942,14 @@ lloid_status lloid_inspect(lloid_plan *P, int32_t what, int32_t index, int32_t d
         const PSlice &s = P->slices[index];
         const int64_t newest = P->stride * s.rate + s.la - 1;
         if (m_hi - 1 > newest || m_lo <= newest - s.capY || len > s.capY) return LLOID_E_STATE;
-        const int64_t pos = ((m_lo % s.capY) + s.capY) % s.capY;
-        for (int l = 0; l < s.L; ++l)
-            HIP_OK(hipMemcpy(dst + l * len, s.yring + det * s.ydet + (int64_t)l * 2 * s.capY + pos,
-                             sizeof(float) * len, hipMemcpyDeviceToHost));
+        float *tmp = nullptr;
+        HIP_OK(hipDeviceSynchronize());
+        HIP_OK(hipMalloc(&tmp, sizeof(float) * (size_t)s.L * len));
+        hipError_t e = launch_ring_gather(nullptr, P->precision, s.yring + det * s.ydet, s.Lpad, s.capY, m_lo,
+                                          (int32_t)len, s.L, tmp, len, 0);
+        if (e == hipSuccess) e = hipMemcpy(dst, tmp, sizeof(float) * (size_t)s.L * len, hipMemcpyDeviceToHost);
+        (void)hipFree(tmp);
+        HIP_OK(e);
         return LLOID_OK;
     }
     return LLOID_E_ARG;
@@ -1045,7 +1055,7 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
             const PSlice &s = P->slices[i];
             const int64_t a = (int64_t)k * s.rate + s.la;
             for (int d = 0; d < ND; ++d)
-                HIP_OK(launch_copy_window(st, s.yring + d * s.ydet, 2LL * s.capY, s.capY, a, s.rate, s.L,
+                HIP_OK(launch_ring_gather(st, LLOID_FP32, s.yring + d * s.ydet, s.Lpad, s.capY, a, s.rate, s.L,
                                           yseg[i] + (int64_t)d * s.Lpad * qld[i], qld[i], a - slo[i]));
         }
         for (auto &kv : dseg) {

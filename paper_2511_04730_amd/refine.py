@@ -1,9 +1,9 @@
 """Bank refinement by gradient descent on the SNR-reconstruction loss.
 
-Each step: loss and gradient from the library (lloid_grad), a plain
-gradient step on float64 master copies, FP64 re-orthonormalisation of the
-bases on the device (lloid_orthonormalize), and the refined slices written
-back into the plan (lloid_set_slice).  The plan must be FP32 with
+Each step: loss and gradient through SnrReconstructionLoss (the library's
+lloid_grad behind torch.autograd, which also writes the current slices into
+the plan), a plain gradient step on float64 master copies, and FP64
+re-orthonormalisation of the bases on the device (lloid_orthonormalize).  The plan must be FP32 with
 normalize = False.
 
 The loss curvature grows with the number of samples in the segment, so the
@@ -13,6 +13,7 @@ from __future__ import annotations
 
 from typing import List, Sequence
 
+from .autograd import bank_loss, bank_parameters
 from .plan import LloidPlan, orthonormalize
 
 
@@ -21,19 +22,21 @@ def refine(plan: LloidPlan, banks: Sequence, strain, target, steps: int, eta: fl
     refined float64 (U, W) per slice (cuda tensors)."""
     import torch
     lr = eta / strain.shape[1]
-    U = [torch.tensor(s.basis, dtype=torch.float64, device="cuda") for b in banks for s in b.slices]
-    W = [torch.tensor(s.mixing, dtype=torch.float64, device="cuda") for b in banks for s in b.slices]
+    U, W = bank_parameters(banks)
     losses: List[float] = []
     for step in range(steps):
-        loss, dW, dU = plan.grad(strain, target)
-        losses.append(loss)
+        loss = bank_loss(plan, strain, target, U, W)
+        loss.backward()
+        losses.append(float(loss))
         if log:
-            log(step, loss)
-        for i in range(len(U)):
-            W[i] -= lr * dW[i].double()
-            U[i] -= lr * dU[i].double()
-            orthonormalize(U[i], W[i])
-            plan.set_slice(i, U[i], W[i])
-    loss, _, _ = plan.grad(strain, target)
-    losses.append(loss)
-    return losses, U, W
+            log(step, losses[-1])
+        with torch.no_grad():
+            for i in range(len(U)):
+                U[i] -= lr * U[i].grad
+                W[i] -= lr * W[i].grad
+                U[i].grad = None
+                W[i].grad = None
+                orthonormalize(U[i].detach(), W[i].detach())
+    with torch.no_grad():
+        losses.append(float(bank_loss(plan, strain, target, U, W)))
+    return losses, [u.detach() for u in U], [w.detach() for w in W]

@@ -103,6 +103,36 @@ def test_gradient_matches_oracle(lib, problem):
         assert ew < tw and eu < tu
 
 
+def test_autograd_function_returns_library_gradient(lib, problem):
+    """SnrReconstructionLoss: forward = lloid_grad's loss (also the oracle's
+    to 1e-4), backward = its gradients times the incoming gradient, for
+    float64 and float32 parameters."""
+    from paper_2511_04730_amd.autograd import bank_loss, bank_parameters
+    bank, x, target, T, cfg = problem
+    plan = lib.LloidPlan([bank], F, 1, "fp32", normalize=False)
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    tg = torch.from_numpy(_target_layout(target, bank.n_templates, T)).cuda()
+    U, W = bank_parameters([bank])
+    loss = bank_loss(plan, xs, tg, U, W)
+    (3.0 * loss).backward()
+    l2, dW, dU = plan.grad(xs, tg)
+    assert float(loss) == l2
+    L_ref, _, _ = O.loss_and_grad(x[0], bank, target, cfg, 0, T * F)
+    assert abs(float(loss) - L_ref) <= 1e-4 * L_ref
+    for i in range(len(U)):
+        assert torch.equal(U[i].grad, 3.0 * dU[i].double())
+        assert torch.equal(W[i].grad, 3.0 * dW[i].double())
+    U32 = [u.detach().float().requires_grad_() for u in U]
+    W32 = [w.detach().float().requires_grad_() for w in W]
+    loss32 = bank_loss(plan, xs, tg, U32, W32)
+    loss32.backward()
+    for i in range(len(U)):
+        assert U32[i].grad.dtype == torch.float32
+        # the float32 parameters are a slightly different bank: the FP32
+        # forward's rounding differs, which moves the (small) residual
+        assert torch.allclose(U32[i].grad, dU[i], rtol=0, atol=2e-3 * float(dU[i].abs().max()))
+
+
 def test_gradient_two_detectors_sums(lib, problem):
     """Detectors share W and U: the gradient is the sum over detectors
     (given residuals E0, E1 as above)."""
