@@ -55,6 +55,38 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+KERNEL_SOURCES = {"mix": ["lloid_mix.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
+                  "corr": ["lloid_corr.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"]}
+
+
+def source_digest(kernel: str) -> str:
+    """sha256 over the sources a kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES[kernel]:
+        with open(os.path.join(ROOT, "paper_2511_04730_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str, precision: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary
+    profiles/traffic_counters.txt (lines: kernel/workload/precision,
+    bytes per launch, source sha256; '#' lines give the commands), i.e.
+    FETCH_SIZE and WRITE_SIZE per dispatch scaled by the copy-kernel
+    calibration; None when there is no entry or the kernel's sources
+    changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.txt")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 3 and not line.startswith("#") and parts[0] == f"{kernel}/{workload}/{precision}":
+                return float(parts[1]) if parts[2] == source_digest(kernel) else None
+    return None
+
+
 def kernel_flops(w) -> dict:
     """Algorithmic flops per launch of the two contraction kernels (all
     banks and detectors)."""
@@ -142,6 +174,8 @@ def main() -> int:
     ap.add_argument("--graph", type=int, default=1, help="replay one HIP graph per stride")
     ap.add_argument("--peaks-only", action="store_true")
     ap.add_argument("--autotune", type=int, default=1, help="tune the tiling options before timing")
+    ap.add_argument("--tiling", default="", help="fixed tiling instead of autotuning, "
+                                                 "e.g. corr_split=8192,corr_group=32,mix_group=16")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
@@ -185,7 +219,12 @@ def main() -> int:
 
     def run(precision: str, profile: bool):
         plan = LloidPlan(w.banks, F, ND, precision)
-        if args.autotune:
+        if args.tiling:
+            for kv in args.tiling.split(","):
+                k, v = kv.split("=")
+                plan.set_option(k.strip(), int(v))
+            tiling[precision] = {k: plan.option(k) for k in ("corr_split", "corr_group", "mix_group")}
+        elif args.autotune:
             from paper_2511_04730_amd.autotune import autotune
             best = autotune(plan, strides[:4], write_series=write, log=log)
             tiling[precision] = {k: best[k] for k in ("corr_split", "corr_group", "mix_group")}
@@ -238,7 +277,7 @@ def main() -> int:
                    "precision": args.precision, "series_written": write, "graph": bool(args.graph),
                    "stride_s": 1, "flops_per_stride": flops_per_stride, "tiling": tiling.get(args.precision)},
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None},
+                     "frac": achieved / peak, "traffic": measured_traffic(dom, args.workload, args.precision)},
         "kernel_ms": kernel_ms,
         "snr_err": err,
         "compare": compare,

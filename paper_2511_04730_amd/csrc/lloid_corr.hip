@@ -1,0 +1,401 @@
+// Per-slice basis correlation (Sec. II.C.2 "Filtering and reconstruction",
+// with the integer read offsets of the pre-synchronisation equation,
+// Sec. II.C.3):
+//   Y[l][c] = sum_n U[l][n] d[k f + off + c + n]
+// as a dense contraction on MFMA: A = U (rows l, K = taps), B = the Hankel
+// window of the stream at the slice rate (K = taps, N = output columns).
+//
+// A work item is one slice and detector, up to kCorrMB x 16 basis rows, up
+// to kCorrTQ = 256 output columns and one split of the taps.  Its four
+// waves own the 16-column blocks cb = wave, wave + 4, ... of the item, so
+// every basis fragment a wave reads from LDS feeds up to four column blocks
+// (and every strain fragment up to kCorrMB row blocks).  Taps advance in
+// stages: the basis tile and the strain segment of the next stage are
+// fetched into registers while the current stage's MFMAs run from LDS.
+//
+// Forms (the Op structs):
+//   F32   v_mfma_f32_16x16x4_f32, one tap per lane and K group;
+//   16-bit v_mfma_f32_16x16x32_{bf16,f16}, eight consecutive taps per lane:
+//         a Hankel fragment d[q + n .. q + n + 7] starts at any element, so
+//         the strain segment is staged as 8 copies shifted by 0..7 and read
+//         from copy (q + n) mod 8 at an aligned offset; the strain is split
+//         on the fly, d = d_hi + d_lo;
+//           SPLIT_U (bf16x3): U_hi d_lo + U_lo d_hi + U_hi d_hi
+//           otherwise (fp16): U d_lo + U d_hi
+//   FP8   v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3 on gfx950): the basis rows
+//         hold e4m3(u_l 2^e_l) with one power-of-two scale per basis vector
+//         (largest |u| near the e4m3 maximum 448), the strain is scaled by
+//         kFp8StrainScale and split into two e4m3 parts; outputs are
+//         rescaled by uscale[l] = 2^-e_l / kFp8StrainScale.
+// The partial sums of a split go to part[l * f + c]; the reduction adds the
+// splits in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "lloid_device.h"
+#include "lloid_internal.h"
+#include "lloid_mfma.h"
+
+namespace lloid {
+
+constexpr int kCB = 4;   // column blocks per wave
+
+constexpr float kFp8StrainScale = 8.0f;
+
+__device__ __forceinline__ uint32_t fp8_byte(float v) {
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xffu;
+}
+__device__ __forceinline__ float fp8_value(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
+
+// strain samples of a stage: kCorrTQ + TK (+ 8 for the shifted copies)
+template <int TK>
+struct StrainRegs {
+    static constexpr int N = kCorrTQ + TK;
+    static constexpr int PER = (N + 255) / 256;
+    float v[PER];
+    // samples past the item's columns + TK are never used: zeros, unread
+    __device__ __forceinline__ void load(const CorrItem &it, int64_t p0, int tid) {
+        const int lim = min(N, it.ncols + TK);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            v[i] = e < lim ? it.ring[p0 + e] : 0.0f;   // mirror ring: p0 + e < 2 cap
+        }
+    }
+};
+
+// ------------------------------------------------------------------ FP32
+struct CorrF32 {
+    static constexpr int TK = 32;
+    static constexpr int US = TK + 2;   // 16 rows x 2 taps of a half-wave in distinct banks
+    struct Smem {
+        float U[kCorrMB * 16 * US];
+        float d[kCorrTQ + TK];
+    };
+    static constexpr int PER = kCorrMB * 16 * (TK / 4) / 256;
+    struct Regs {
+        float4 u[PER];
+        StrainRegs<TK> d;
+    };
+    static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (TK / 4), c4 = e % (TK / 4);
+            if (r < it.mb * 16)
+                g.u[i] = *reinterpret_cast<const float4 *>(it.U + (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 4 * c4);
+        }
+        g.d.load(it, p0, tid);
+    }
+    static __device__ __forceinline__ void lstore(const Regs &g, Smem &s, const CorrItem &it, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (TK / 4), c4 = e % (TK / 4);
+            if (r < it.mb * 16) {
+                float *u = &s.U[r * US + 4 * c4];
+                u[0] = g.u[i].x;
+                u[1] = g.u[i].y;
+                u[2] = g.u[i].z;
+                u[3] = g.u[i].w;
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < StrainRegs<TK>::PER; ++i) {
+            const int e = tid + 256 * i;
+            if (e < StrainRegs<TK>::N) s.d[e] = g.d.v[i];
+        }
+    }
+    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][kCB], int mb, int ncb,
+                                                   int wave, int li, int lg) {
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 4) {
+            float b[kCB];
+#pragma unroll
+            for (int i = 0; i < kCB; ++i) b[i] = s.d[(wave + 4 * i) * 16 + li + ks + lg];
+#pragma unroll
+            for (int m = 0; m < kCorrMB; ++m) {
+                if (m >= mb) continue;
+                const float a = s.U[(m * 16 + li) * US + ks + lg];
+#pragma unroll
+                for (int i = 0; i < kCB; ++i)
+                    if (i < ncb) acc[m][i] = mfma_16x16x4_f32(a, b[i], acc[m][i]);
+            }
+        }
+    }
+    static __device__ __forceinline__ float scale(const CorrItem &, int) { return 1.0f; }
+};
+
+// ---------------------------------------------------------------- 16-bit
+template <typename T, typename T8, bool SPLIT_U>
+struct Corr16 {
+    static constexpr int TK = 64;
+    static constexpr int US = TK + 8;   // 144 B rows: 16-B fragment reads of a half-wave in distinct banks
+    static constexpr int DL = kCorrTQ + TK + 8;
+    struct Smem {
+        T Uh[kCorrMB * 16 * US];
+        T Ul[SPLIT_U ? kCorrMB * 16 * US : 8];
+        T Dh[8 * DL];
+        T Dl[8 * DL];
+    };
+    static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
+    struct Regs {
+        uint4 uh[PER], ul[SPLIT_U ? PER : 1];
+        StrainRegs<TK> d;
+    };
+    static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
+        const T *gh = static_cast<const T *>(it.Uhi);
+        const T *gl = static_cast<const T *>(it.Ulo);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (TK / 8), c8 = e % (TK / 8);
+            if (r < it.mb * 16) {
+                const int64_t o = (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 8 * c8;
+                g.uh[i] = *reinterpret_cast<const uint4 *>(gh + o);
+                if constexpr (SPLIT_U) g.ul[i] = *reinterpret_cast<const uint4 *>(gl + o);
+            }
+        }
+        g.d.load(it, p0, tid);
+    }
+    static __device__ __forceinline__ void lstore(const Regs &g, Smem &s, const CorrItem &it, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (TK / 8), c8 = e % (TK / 8);
+            if (r < it.mb * 16) {
+                *reinterpret_cast<uint4 *>(&s.Uh[r * US + 8 * c8]) = g.uh[i];
+                if constexpr (SPLIT_U) *reinterpret_cast<uint4 *>(&s.Ul[r * US + 8 * c8]) = g.ul[i];
+            }
+        }
+        // copy sft holds d[i + sft] at position i
+#pragma unroll
+        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= StrainRegs<TK>::N) continue;
+            const float v = g.d.v[k];
+            const T h = (T)v;
+            const T l = (T)(v - (float)h);
+#pragma unroll
+            for (int sft = 0; sft < 8; ++sft) {
+                const int i = e - sft;
+                if (i >= 0) {
+                    s.Dh[sft * DL + i] = h;
+                    s.Dl[sft * DL + i] = l;
+                }
+            }
+        }
+    }
+    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][kCB], int mb, int ncb,
+                                                   int wave, int li, int lg) {
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 32) {
+            T8 bh[kCB], bl[kCB];
+#pragma unroll
+            for (int i = 0; i < kCB; ++i) {
+                const int idx = (wave + 4 * i) * 16 + li + ks + 8 * lg;
+                const int sft = idx & 7;
+                bh[i] = *reinterpret_cast<const T8 *>(&s.Dh[sft * DL + idx - sft]);
+                bl[i] = *reinterpret_cast<const T8 *>(&s.Dl[sft * DL + idx - sft]);
+            }
+#pragma unroll
+            for (int m = 0; m < kCorrMB; ++m) {
+                if (m >= mb) continue;
+                const int off = (m * 16 + li) * US + ks + 8 * lg;
+                const T8 ah = *reinterpret_cast<const T8 *>(&s.Uh[off]);
+                T8 al;
+                if constexpr (SPLIT_U) al = *reinterpret_cast<const T8 *>(&s.Ul[off]);
+#pragma unroll
+                for (int i = 0; i < kCB; ++i) {
+                    if (i >= ncb) continue;
+                    acc[m][i] = mfma16(ah, bl[i], acc[m][i]);
+                    if constexpr (SPLIT_U) acc[m][i] = mfma16(al, bh[i], acc[m][i]);
+                    acc[m][i] = mfma16(ah, bh[i], acc[m][i]);
+                }
+            }
+        }
+    }
+    static __device__ __forceinline__ float scale(const CorrItem &, int) { return 1.0f; }
+};
+
+// ------------------------------------------------------------------ FP8
+struct Corr8 {
+    static constexpr int TK = 64;
+    static constexpr int US = TK + 16;   // bytes per basis row
+    static constexpr int DL = kCorrTQ + TK + 8;
+    struct Smem {
+        uint8_t U[kCorrMB * 16 * US];
+        uint8_t Dh[8 * DL];
+        uint8_t Dl[8 * DL];
+    };
+    static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
+    struct Regs {
+        uint2 u[PER];
+        StrainRegs<TK> d;
+    };
+    static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
+        const uint8_t *gu = static_cast<const uint8_t *>(it.Uhi);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (TK / 8), c8 = e % (TK / 8);
+            if (r < it.mb * 16)
+                g.u[i] = *reinterpret_cast<const uint2 *>(gu + (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 8 * c8);
+        }
+        g.d.load(it, p0, tid);
+    }
+    static __device__ __forceinline__ void lstore(const Regs &g, Smem &s, const CorrItem &it, int tid) {
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int e = tid + 256 * i;
+            const int r = e / (TK / 8), c8 = e % (TK / 8);
+            if (r < it.mb * 16) *reinterpret_cast<uint2 *>(&s.U[r * US + 8 * c8]) = g.u[i];
+        }
+#pragma unroll
+        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= StrainRegs<TK>::N) continue;
+            // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
+            const float v = fminf(fmaxf(g.d.v[k] * kFp8StrainScale, -448.0f), 448.0f);
+            const uint32_t h = fp8_byte(v);
+            const uint32_t l = fp8_byte(v - fp8_value(h));
+#pragma unroll
+            for (int sft = 0; sft < 8; ++sft) {
+                const int i = e - sft;
+                if (i >= 0) {
+                    s.Dh[sft * DL + i] = (uint8_t)h;
+                    s.Dl[sft * DL + i] = (uint8_t)l;
+                }
+            }
+        }
+    }
+    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][kCB], int mb, int ncb,
+                                                   int wave, int li, int lg) {
+#pragma unroll
+        for (int ks = 0; ks < TK; ks += 32) {
+            long bh[kCB], bl[kCB];
+#pragma unroll
+            for (int i = 0; i < kCB; ++i) {
+                const int idx = (wave + 4 * i) * 16 + li + ks + 8 * lg;
+                const int sft = idx & 7;
+                bh[i] = *reinterpret_cast<const long *>(&s.Dh[sft * DL + idx - sft]);
+                bl[i] = *reinterpret_cast<const long *>(&s.Dl[sft * DL + idx - sft]);
+            }
+#pragma unroll
+            for (int m = 0; m < kCorrMB; ++m) {
+                if (m >= mb) continue;
+                const long a = *reinterpret_cast<const long *>(&s.U[(m * 16 + li) * US + ks + 8 * lg]);
+#pragma unroll
+                for (int i = 0; i < kCB; ++i) {
+                    if (i >= ncb) continue;
+                    acc[m][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bl[i], acc[m][i], 0, 0, 0);
+                    acc[m][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bh[i], acc[m][i], 0, 0, 0);
+                }
+            }
+        }
+    }
+    static __device__ __forceinline__ float scale(const CorrItem &it, int row) { return it.uscale[it.r0 + row]; }
+};
+
+// ------------------------------------------------------------------ kernel
+template <typename Op>
+__global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict__ items, int32_t n_items,
+                                                      int32_t group, const int64_t *__restrict__ stride_ctr) {
+    __shared__ __attribute__((aligned(16))) typename Op::Smem sm;
+    const int item = xcd_item(group);
+    if (item >= n_items) return;
+    const CorrItem it = items[item];
+    const int64_t kstr = *stride_ctr;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    // this wave's column blocks cb = wave + 4 i, i < ncb
+    const int ncb = min(kCB, max(0, (((it.ncols + 15) >> 4) - wave + 3) >> 2));
+
+    floatx4 acc[kCorrMB][kCB];
+#pragma unroll
+    for (int m = 0; m < kCorrMB; ++m)
+#pragma unroll
+        for (int i = 0; i < kCB; ++i) acc[m][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
+    typename Op::Regs g;
+    Op::gload(g, it, posmod(dbase, it.cap), 0, tid);
+    for (int kk = 0; kk < it.klen; kk += Op::TK) {
+        __syncthreads();   // the previous stage's LDS reads are done
+        Op::lstore(g, sm, it, tid);
+        __syncthreads();
+        if (kk + Op::TK < it.klen) Op::gload(g, it, posmod(dbase + kk + Op::TK, it.cap), kk + Op::TK, tid);
+        Op::compute(sm, acc, it.mb, ncb, wave, li, lg);
+    }
+#pragma unroll
+    for (int i = 0; i < kCB; ++i) {
+        if (i >= ncb) continue;
+        const int c = (wave + 4 * i) * 16 + li;
+        if (c >= it.ncols) continue;
+#pragma unroll
+        for (int m = 0; m < kCorrMB; ++m) {
+            if (m >= it.mb) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = m * 16 + lg * 4 + v;
+                it.part[(int64_t)(it.r0 + r) * it.f + it.col0 + c] = acc[m][i][v] * Op::scale(it, r);
+            }
+        }
+    }
+}
+
+// Basis rows to e4m3 with a power-of-two scale per row: one block per row,
+// e = floor(log2(448 / max|u|)); dst = e4m3(u 2^e); scale[r] = 2^-e / kFp8StrainScale.
+__global__ __launch_bounds__(256) void convert_fp8_rows_kernel(const double *__restrict__ src, int32_t cols,
+                                                               int32_t src_ld, uint8_t *__restrict__ dst,
+                                                               int32_t dst_ld, float *__restrict__ scale) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
+    double mx = 0.0;
+    for (int c = threadIdx.x; c < cols; c += 256) mx = fmax(mx, fabs(src[(int64_t)r * src_ld + c]));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const int e = red[0] > 0.0 ? (int)floor(log2(448.0 / red[0])) : 0;
+    const double s = ldexp(1.0, e);
+    for (int c = threadIdx.x; c < cols; c += 256)
+        dst[(int64_t)r * dst_ld + c] = (uint8_t)fp8_byte((float)(src[(int64_t)r * src_ld + c] * s));
+    if (threadIdx.x == 0) scale[r] = (float)(ldexp(1.0, -e) / kFp8StrainScale);
+}
+
+hipError_t launch_convert_fp8_rows(hipStream_t st, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
+                                   uint8_t *dst, int32_t dst_ld, float *scale) {
+    hipLaunchKernelGGL(convert_fp8_rows_kernel, dim3(rows), dim3(256), 0, st, src, cols, src_ld, dst, dst_ld, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items, int32_t group) {
+    if (n_items == 0) return hipSuccess;
+    const dim3 grid(xcd_grid(n_items, group));
+    switch (precision) {
+        case LLOID_FP32:
+            hipLaunchKernelGGL(corr_kernel<CorrF32>, grid, dim3(256), 0, ctx.stream, items, n_items, group,
+                               ctx.stride_ctr);
+            break;
+        case LLOID_FP8_BF16:
+            hipLaunchKernelGGL(corr_kernel<Corr8>, grid, dim3(256), 0, ctx.stream, items, n_items, group,
+                               ctx.stride_ctr);
+            break;
+        case LLOID_BF16X3:
+            hipLaunchKernelGGL((corr_kernel<Corr16<__bf16, bf16x8, true>>), grid, dim3(256), 0, ctx.stream, items,
+                               n_items, group, ctx.stride_ctr);
+            break;
+        case LLOID_FP16:
+            hipLaunchKernelGGL((corr_kernel<Corr16<_Float16, halfx8, false>>), grid, dim3(256), 0, ctx.stream, items,
+                               n_items, group, ctx.stride_ctr);
+            break;
+        default:
+            return hipErrorNotSupported;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace lloid

@@ -24,6 +24,17 @@ __device__ __forceinline__ bool better(float p2, int idx, float bp2, int bidx) {
     return p2 > bp2 || (p2 == bp2 && idx < bidx);
 }
 
+// Raw buffer resource over [base, base + bytes) (gfx9 descriptor word 3);
+// loads through it take a 32-bit per-lane offset plus a scalar offset, and
+// return zero outside the range.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+template <typename V>
+__device__ __forceinline__ V buffer_load16(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
+
 // Work item of this work group when `group` consecutive items are to share
 // one XCD (and its L2): the dispatcher deals work groups to the XCDs in turn,
 // so group b runs on XCD b mod kXcds.  group <= 0 keeps the launch order.

@@ -12,12 +12,17 @@ namespace lloid {
 // ---------------------------------------------------------------- constants
 constexpr int kMaxLevels = 12;        // distinct rates per bank (top included)
 constexpr int kMaxBasis = 160;        // L^s limit, and per bank and rate (ABI)
-constexpr int kCorrTQ = 64;           // correlation tile: output columns
-constexpr int kCorrTK = 64;           // correlation tile: taps staged per step
+constexpr int kCorrTQ = 256;          // correlation item: output columns (64 per wave)
+constexpr int kCorrMB = 8;            // correlation item: 16-row blocks of basis vectors
+constexpr int kCorrTK = 64;           // tap padding of the basis rows
 constexpr int kCorrSplitK = 512;      // taps per correlation work item
-constexpr int kMixTM = 32;            // mixing tile: real rows (16 templates)
+constexpr int kMixTM = 128;           // mixing tile: real rows (64 templates)
 constexpr int kMixTN = 256;           // mixing tile: top-rate samples
 constexpr int kUpTaps = 17;           // 2 N_up + 1 taps per polyphase branch
+// mixing level-buffer row stride (floats): at least the widest window of a
+// lower level, kMixTN / 2 + 2 N_up + 1 <= 145, and 18 mod 32 (the
+// upsampling's 16 rows x 2 columns per half-wave fall in distinct banks)
+constexpr int kMixS = 146;
 constexpr int kMaxLdsBytes = 96 * 1024;   // dynamic LDS per work group we allow (160 KB on gfx950)
 constexpr int kXcds = 8;              // accelerator complex dies of the MI355X
 
@@ -31,8 +36,9 @@ inline int xcd_grid(int n_items, int group) {
 // -------------------------------------------------------------- work items
 // Basis correlation (Sec. II.C.2 "Filtering and reconstruction"):
 //   y_l[q] = sum_n u_l[n] d[q + n + off],  off = -delay - (N-1)
-// for the f new columns q = k f + la + c, c in [col0, col0+ncols), taps
-// n in [k0, k0+klen).  The partial result goes to part[l * f + c].
+// for the f new columns q = k f + la + c, c in [col0, col0+ncols), basis
+// rows l in [r0, r0 + 16 mb), taps n in [k0, k0+klen).  The partial result
+// goes to part[l * f + c].
 struct CorrItem {
     const float *U;          // [Lpad][Npad] fp32 (FP32 mode)
     const void *Uhi;         // reduced-precision basis, [Lpad][Npad]
@@ -43,8 +49,8 @@ struct CorrItem {
     int64_t off;             // la - delay - (N - 1)  (index = k f + off + c + n)
     int32_t Npad, Lpad, cap, f;
     int32_t col0, ncols, k0, klen;
-    int32_t mb;              // Lpad / 16
-    int32_t pad_;
+    int32_t mb;              // 16-row blocks of this item (<= kCorrMB)
+    int32_t r0;              // first basis row of this item
 };
 
 // Deterministic split-K reduction of 64 new columns of one slice and
@@ -78,6 +84,8 @@ struct MixSlice {
     const void *Y;           // basis-output ring of detector 0
     int64_t ydet;            // 4-byte elements between detectors' rings
     int32_t L, Lpad, capY, level;
+    int32_t rows_pad;        // rows of W (a multiple of kMixTM)
+    int32_t pad_;
 };
 
 struct MixBank {
@@ -90,7 +98,7 @@ struct MixBank {
     int32_t shp[kMaxLevels];     // log2 p
     int32_t lo[kMaxLevels];      // window start of tile t0 = 0, local index
     int32_t n[kMaxLevels];       // window length
-    int32_t up_off[kMaxLevels];  // offset of level j's sub-kernels in the tap table
+    int32_t up_off[kMaxLevels];  // offset of stage j's sub-kernels in the bank's LDS tap copy
     int32_t slice_begin[kMaxLevels + 1];  // MixSlice range per level
     int64_t series_off;          // float offset of the bank's series block
     int64_t peak_off;            // entry offset of the bank's peak block
@@ -129,13 +137,13 @@ hipError_t launch_reduce(const LaunchCtx &, int precision, const ReduceItem *ite
 hipError_t launch_mix(const LaunchCtx &, int precision, const MixItem *items, int32_t n_items,
                       const MixBank *banks, const MixSlice *slices, const float *uptaps,
                       float *series, PartialPeak *partials, int32_t F, int32_t n_det,
-                      int32_t S, int32_t SW, int32_t nup, int32_t group);
+                      int32_t S, int32_t TP, int32_t nup, int32_t group);
 hipError_t launch_peaks(const LaunchCtx &, const PeakItem *items, int32_t n_items,
                         const PartialPeak *partials, lloid_peak *peaks, float threshold,
                         int64_t *stride_ctr_advance);
 hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes);
-size_t mix_lds(int precision, int S);   // dynamic LDS bytes of the mix kernel
-inline size_t mix_lds_bytes(int precision, int S) { return mix_lds(precision, S); }
+size_t mix_lds(int precision, int S, int TP);   // dynamic LDS bytes of the mix kernel
+inline size_t mix_lds_bytes(int precision, int S, int TP) { return mix_lds(precision, S, TP); }
 // FP8 e4m3 rows with one power-of-two scale per row (basis role of LLOID_FP8_BF16)
 hipError_t launch_convert_fp8_rows(hipStream_t, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
                                    uint8_t *dst, int32_t dst_ld, float *scale);

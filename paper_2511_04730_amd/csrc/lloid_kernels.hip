@@ -5,6 +5,7 @@
 //   down      decimation to every slice rate, Eq. (sinc) kernel, zero phase
 //   corr      per-slice basis correlation, a Hankel(strain) x basis
 //             contraction on MFMA with LDS-staged tiles, split over taps
+//             (lloid_corr.hip)
 //   reduce    fixed-order sum of the tap splits into the basis-output ring
 //   mix       mixing-matrix contraction on MFMA fused with the polyphase
 //             upsample-and-add chain (lowest rate first), the SNR series
@@ -85,387 +86,6 @@ hipError_t launch_down(const LaunchCtx &ctx, const DownItem *items, int32_t n_it
     if (n_items == 0) return hipSuccess;
     hipLaunchKernelGGL(down_kernel, dim3(n_items), dim3(256), (size_t)max_lds_floats * sizeof(float), ctx.stream,
                        items, ctx.stride_ctr);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------- basis correlation
-// Y[l][c] = sum_n U[l][n] d[k f + off + c + n]: A = U (rows l, K = taps),
-// B = Hankel window of the stream (K = taps, N = columns), on
-// v_mfma_f32_16x16x4_f32.  The work group owns all Lpad rows and 64 columns
-// (one 16-column block per wave); taps advance in chunks of kCorrTK staged
-// in LDS: the basis tile row-major with row stride kCorrTK + 2 (the 16 rows x
-// 2 taps a half-wave reads fall in distinct banks) and the strain segment
-// kCorrTQ + kCorrTK long, from which every lane reads its Hankel entry.
-constexpr int kTKF = 32;             // taps per LDS stage
-constexpr int kUS = kTKF + 2;
-
-template <int MBMAX>
-__global__ __launch_bounds__(256) void corr_f32_kernel(const CorrItem *__restrict__ items, int32_t n_items,
-                                                       int32_t group, const int64_t *__restrict__ stride_ctr) {
-    // double-buffered: the next stage's tiles are loaded into registers while
-    // the current stage's MFMAs run from LDS
-    __shared__ float Us[2][MBMAX * 16 * kUS];
-    __shared__ float ds[2][kCorrTQ + kTKF];
-    constexpr int PER = (MBMAX * 16 * (kTKF / 2) + 255) / 256;
-    const int item = xcd_item(group);
-    if (item >= n_items) return;
-    const CorrItem it = items[item];
-    const int64_t kstr = *stride_ctr;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int rows = it.mb * 16;
-
-    floatx4 acc[MBMAX];
-#pragma unroll
-    for (int m = 0; m < MBMAX; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
-    float2 ureg[PER];
-    float dreg = 0.0f;
-    auto gload = [&](int kk) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = tid + 256 * i;
-            if (e < rows * (kTKF / 2)) {
-                const int r = e / (kTKF / 2), t2 = e % (kTKF / 2);
-                ureg[i] = *reinterpret_cast<const float2 *>(it.U + (int64_t)r * it.Npad + it.k0 + kk + 2 * t2);
-            }
-        }
-        const int64_t p0 = posmod(dbase + kk, it.cap);
-        if (tid < kCorrTQ + kTKF) dreg = it.ring[p0 + tid];
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = tid + 256 * i;
-            if (e < rows * (kTKF / 2)) {
-                const int r = e / (kTKF / 2), t2 = e % (kTKF / 2);
-                Us[buf][r * kUS + 2 * t2] = ureg[i].x;
-                Us[buf][r * kUS + 2 * t2 + 1] = ureg[i].y;
-            }
-        }
-        if (tid < kCorrTQ + kTKF) ds[buf][tid] = dreg;
-    };
-    const int nchunks = it.klen / kTKF;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int c = 0; c < nchunks; ++c) {
-        const int buf = c & 1;
-        if (c + 1 < nchunks) gload((c + 1) * kTKF);
-#pragma unroll
-        for (int ks = 0; ks < kTKF; ks += 4) {
-            const float b = ds[buf][wave * 16 + li + ks + lk];
-#pragma unroll
-            for (int m = 0; m < MBMAX; ++m) {
-                if (m < it.mb) {
-                    const float a = Us[buf][(m * 16 + li) * kUS + ks + lk];
-                    acc[m] = mfma_16x16x4_f32(a, b, acc[m]);
-                }
-            }
-        }
-        if (c + 1 < nchunks) lstore(buf ^ 1);
-        __syncthreads();
-    }
-    const int c = wave * 16 + li;
-    if (c < it.ncols) {
-#pragma unroll
-        for (int m = 0; m < MBMAX; ++m) {
-            if (m < it.mb) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = m * 16 + lk * 4 + v;
-                    it.part[(int64_t)r * it.f + it.col0 + c] = acc[m][v];
-                }
-            }
-        }
-    }
-}
-
-// 16-bit correlation on v_mfma_f32_16x16x32_{bf16,f16}: eight consecutive
-// taps per lane and K-group.  The basis tile is staged row-major with row
-// stride 72 elements (144 B = 16 mod 128, 16-B fragment reads of a half-wave
-// in distinct banks).  A Hankel fragment d[q + n .. q + n + 7] starts at an
-// arbitrary element, so the strain segment is staged as 8 copies shifted by
-// 0..7 elements: the fragment is read from copy (q + n) mod 8 at an aligned
-// offset.  The strain is split on the fly, d = d_hi + d_lo.
-//   SPLIT_U (bf16x3): U_hi d_lo + U_lo d_hi + U_hi d_hi
-//   otherwise (fp16): U d_lo + U d_hi
-template <typename T, typename T8, bool SPLIT_U>
-__global__ __launch_bounds__(256) void corr16_kernel(const CorrItem *__restrict__ items, int32_t n_items,
-                                                     int32_t group, const int64_t *__restrict__ stride_ctr) {
-    constexpr int TK = 64;
-    constexpr int US = TK + 8;
-    constexpr int MBMAX = kMaxBasis / 16;
-    constexpr int DL = kCorrTQ + TK + 8;
-    __shared__ __attribute__((aligned(16))) T Uh[MBMAX * 16 * US];
-    __shared__ __attribute__((aligned(16))) T Ul[SPLIT_U ? MBMAX * 16 * US : 8];
-    __shared__ __attribute__((aligned(16))) T Dh[8 * DL];
-    __shared__ __attribute__((aligned(16))) T Dl[8 * DL];
-    const int item = xcd_item(group);
-    if (item >= n_items) return;
-    const CorrItem it = items[item];
-    const int64_t kstr = *stride_ctr;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int rows = it.mb * 16;
-    const T *gh = static_cast<const T *>(it.Uhi);
-    const T *gl = static_cast<const T *>(it.Ulo);
-
-    floatx4 acc[MBMAX];
-#pragma unroll
-    for (int m = 0; m < MBMAX; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
-    // the next stage's basis tile and strain element are fetched into
-    // registers while the current stage's MFMAs run from LDS
-    constexpr int PER = (MBMAX * 16 * (TK / 8) + 255) / 256;
-    uint4 uh[PER], ul[PER];
-    float dv = 0.0f;
-    auto gload = [&](int kk) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = tid + 256 * i;
-            if (e < rows * (TK / 8)) {
-                const int r = e / (TK / 8), c8 = e % (TK / 8);
-                const int64_t g = (int64_t)r * it.Npad + it.k0 + kk + 8 * c8;
-                uh[i] = *reinterpret_cast<const uint4 *>(gh + g);
-                if (SPLIT_U) ul[i] = *reinterpret_cast<const uint4 *>(gl + g);
-            }
-        }
-        if (tid < kCorrTQ + TK) dv = it.ring[posmod(dbase + kk, it.cap) + tid];
-    };
-    auto lstore = [&]() {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = tid + 256 * i;
-            if (e < rows * (TK / 8)) {
-                const int r = e / (TK / 8), c8 = e % (TK / 8);
-                *reinterpret_cast<uint4 *>(&Uh[r * US + 8 * c8]) = uh[i];
-                if (SPLIT_U) *reinterpret_cast<uint4 *>(&Ul[r * US + 8 * c8]) = ul[i];
-            }
-        }
-        if (tid < kCorrTQ + TK) {
-            const T h = (T)dv;
-            const T l = (T)(dv - (float)h);
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int i = tid - s;
-                if (i >= 0 && i < DL) {
-                    Dh[s * DL + i] = h;
-                    Dl[s * DL + i] = l;
-                }
-            }
-        }
-    };
-    gload(0);
-    for (int kk = 0; kk < it.klen; kk += TK) {
-        __syncthreads();
-        lstore();
-        __syncthreads();
-        if (kk + TK < it.klen) gload(kk + TK);
-#pragma unroll
-        for (int ks = 0; ks < TK; ks += 32) {
-            const int idx = wave * 16 + li + ks + 8 * lk;
-            const int sft = idx & 7;
-            const T8 bh = *reinterpret_cast<const T8 *>(&Dh[sft * DL + idx - sft]);
-            const T8 bl = *reinterpret_cast<const T8 *>(&Dl[sft * DL + idx - sft]);
-#pragma unroll
-            for (int m = 0; m < MBMAX; ++m) {
-                if (m < it.mb) {
-                    const int off = (m * 16 + li) * US + ks + 8 * lk;
-                    const T8 ah = *reinterpret_cast<const T8 *>(&Uh[off]);
-                    acc[m] = mfma16(ah, bl, acc[m]);
-                    if (SPLIT_U) acc[m] = mfma16(*reinterpret_cast<const T8 *>(&Ul[off]), bh, acc[m]);
-                    acc[m] = mfma16(ah, bh, acc[m]);
-                }
-            }
-        }
-    }
-    const int c = wave * 16 + li;
-    if (c < it.ncols) {
-#pragma unroll
-        for (int m = 0; m < MBMAX; ++m) {
-            if (m < it.mb) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = m * 16 + lk * 4 + v;
-                    it.part[(int64_t)r * it.f + it.col0 + c] = acc[m][v];
-                }
-            }
-        }
-    }
-}
-
-// FP8 correlation on v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3 on gfx950): the
-// basis rows hold e4m3(u_l 2^e_l) with a power-of-two scale per basis vector
-// chosen at plan time (largest |u| near the e4m3 maximum 448); the strain is
-// scaled by kFp8StrainScale and split into two e4m3 parts, d = d_hi + d_lo.
-// Eight consecutive taps per lane are one 64-bit operand; the Hankel side
-// again comes from eight shifted LDS copies.  Output rows are rescaled by
-// uscale[l] = 2^-e_l / kFp8StrainScale.
-constexpr float kFp8StrainScale = 8.0f;
-
-__device__ __forceinline__ uint32_t fp8_byte(float v) {
-    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(v, 0.0f, 0, false) & 0xffu;
-}
-__device__ __forceinline__ float fp8_value(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
-
-__global__ __launch_bounds__(256) void corr8_kernel(const CorrItem *__restrict__ items, int32_t n_items,
-                                                    int32_t group, const int64_t *__restrict__ stride_ctr) {
-    constexpr int TK = 64;
-    constexpr int US = TK + 16;            // bytes per basis row in LDS
-    constexpr int MBMAX = kMaxBasis / 16;
-    constexpr int DL = kCorrTQ + TK + 8;   // bytes per shifted copy
-    __shared__ __attribute__((aligned(16))) uint8_t U8[MBMAX * 16 * US];
-    __shared__ __attribute__((aligned(16))) uint8_t Dh[8 * DL];
-    __shared__ __attribute__((aligned(16))) uint8_t Dl[8 * DL];
-    const int item = xcd_item(group);
-    if (item >= n_items) return;
-    const CorrItem it = items[item];
-    const int64_t kstr = *stride_ctr;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
-    const int li = lane & 15, lk = lane >> 4;
-    const int rows = it.mb * 16;
-    const uint8_t *gu = static_cast<const uint8_t *>(it.Uhi);
-
-    floatx4 acc[MBMAX];
-#pragma unroll
-    for (int m = 0; m < MBMAX; ++m) acc[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
-    constexpr int PER = (MBMAX * 16 * (TK / 8) + 255) / 256;
-    uint2 ur[PER];
-    float dv = 0.0f;
-    auto gload = [&](int kk) {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = tid + 256 * i;
-            if (e < rows * (TK / 8)) {
-                const int r = e / (TK / 8), c8 = e % (TK / 8);
-                ur[i] = *reinterpret_cast<const uint2 *>(gu + (int64_t)r * it.Npad + it.k0 + kk + 8 * c8);
-            }
-        }
-        if (tid < kCorrTQ + TK) dv = it.ring[posmod(dbase + kk, it.cap) + tid];
-    };
-    auto lstore = [&]() {
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int e = tid + 256 * i;
-            if (e < rows * (TK / 8)) {
-                const int r = e / (TK / 8), c8 = e % (TK / 8);
-                *reinterpret_cast<uint2 *>(&U8[r * US + 8 * c8]) = ur[i];
-            }
-        }
-        if (tid < kCorrTQ + TK) {
-            // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
-            const float v = fminf(fmaxf(dv * kFp8StrainScale, -448.0f), 448.0f);
-            const uint32_t h = fp8_byte(v);
-            const uint32_t l = fp8_byte(v - fp8_value(h));
-#pragma unroll
-            for (int s = 0; s < 8; ++s) {
-                const int i = tid - s;
-                if (i >= 0 && i < DL) {
-                    Dh[s * DL + i] = (uint8_t)h;
-                    Dl[s * DL + i] = (uint8_t)l;
-                }
-            }
-        }
-    };
-    gload(0);
-    for (int kk = 0; kk < it.klen; kk += TK) {
-        __syncthreads();
-        lstore();
-        __syncthreads();
-        if (kk + TK < it.klen) gload(kk + TK);
-#pragma unroll
-        for (int ks = 0; ks < TK; ks += 32) {
-            const int idx = wave * 16 + li + ks + 8 * lk;
-            const int sft = idx & 7;
-            const long bh = *reinterpret_cast<const long *>(&Dh[sft * DL + idx - sft]);
-            const long bl = *reinterpret_cast<const long *>(&Dl[sft * DL + idx - sft]);
-#pragma unroll
-            for (int m = 0; m < MBMAX; ++m) {
-                if (m < it.mb) {
-                    const long a = *reinterpret_cast<const long *>(&U8[(m * 16 + li) * US + ks + 8 * lk]);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bl, acc[m], 0, 0, 0);
-                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bh, acc[m], 0, 0, 0);
-                }
-            }
-        }
-    }
-    const int c = wave * 16 + li;
-    if (c < it.ncols) {
-#pragma unroll
-        for (int m = 0; m < MBMAX; ++m) {
-            if (m < it.mb) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = m * 16 + lk * 4 + v;
-                    it.part[(int64_t)r * it.f + it.col0 + c] = acc[m][v] * it.uscale[r];
-                }
-            }
-        }
-    }
-}
-
-// Basis rows to e4m3 with a power-of-two scale per row: one block per row,
-// e = floor(log2(448 / max|u|)); dst = e4m3(u 2^e); scale[r] = 2^-e / kFp8StrainScale.
-__global__ __launch_bounds__(256) void convert_fp8_rows_kernel(const double *__restrict__ src, int32_t cols,
-                                                               int32_t src_ld, uint8_t *__restrict__ dst,
-                                                               int32_t dst_ld, float *__restrict__ scale) {
-    __shared__ double red[256];
-    const int r = blockIdx.x;
-    double mx = 0.0;
-    for (int c = threadIdx.x; c < cols; c += 256) mx = fmax(mx, fabs(src[(int64_t)r * src_ld + c]));
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
-        __syncthreads();
-    }
-    const int e = red[0] > 0.0 ? (int)floor(log2(448.0 / red[0])) : 0;
-    const double s = ldexp(1.0, e);
-    for (int c = threadIdx.x; c < cols; c += 256)
-        dst[(int64_t)r * dst_ld + c] = (uint8_t)fp8_byte((float)(src[(int64_t)r * src_ld + c] * s));
-    if (threadIdx.x == 0) scale[r] = (float)(ldexp(1.0, -e) / kFp8StrainScale);
-}
-
-hipError_t launch_convert_fp8_rows(hipStream_t st, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
-                                   uint8_t *dst, int32_t dst_ld, float *scale) {
-    hipLaunchKernelGGL(convert_fp8_rows_kernel, dim3(rows), dim3(256), 0, st, src, cols, src_ld, dst, dst_ld, scale);
-    return hipGetLastError();
-}
-
-hipError_t launch_corr_reduced(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items,
-                               int32_t group) {
-    const dim3 grid(xcd_grid(n_items, group));
-    switch (precision) {
-        case LLOID_FP8_BF16:
-            hipLaunchKernelGGL(corr8_kernel, grid, dim3(256), 0, ctx.stream, items, n_items, group, ctx.stride_ctr);
-            break;
-        case LLOID_BF16X3:
-            hipLaunchKernelGGL((corr16_kernel<__bf16, bf16x8, true>), grid, dim3(256), 0, ctx.stream, items, n_items,
-                               group, ctx.stride_ctr);
-            break;
-        case LLOID_FP16:
-            hipLaunchKernelGGL((corr16_kernel<_Float16, halfx8, false>), grid, dim3(256), 0, ctx.stream, items,
-                               n_items, group, ctx.stride_ctr);
-            break;
-        default:
-            return hipErrorNotSupported;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_corr(const LaunchCtx &ctx, int precision, const CorrItem *items, int32_t n_items, int32_t group) {
-    if (n_items == 0) return hipSuccess;
-    if (precision != LLOID_FP32) return launch_corr_reduced(ctx, precision, items, n_items, group);
-    hipLaunchKernelGGL(corr_f32_kernel<kMaxBasis / 16>, dim3(xcd_grid(n_items, group)), dim3(256), 0, ctx.stream,
-                       items, n_items, group, ctx.stride_ctr);
     return hipGetLastError();
 }
 

@@ -13,7 +13,8 @@
 // series (interleaved re, im) and to the running trigger candidates.
 //
 // Both operands of the mixing contraction come straight from memory into
-// MFMA registers, with no LDS staging and no barrier: W~ rows are row-major
+// MFMA registers (buffer loads, double-buffered over basis-row steps), with
+// no LDS staging and no barrier: W~ rows are row-major
 // [rows][Lpad] and the basis-output rings are time-major [position][Lpad]
 // (one row per sample), so the K elements a lane supplies (8 consecutive
 // basis rows for the 16-bit forms, 4 for FP32) are one 16-byte load on
@@ -41,8 +42,13 @@
 
 namespace lloid {
 
-constexpr int kRB = kMixTM / 16;   // 16-row blocks per work group
-constexpr int kCB = 4;             // column blocks per wave (4 waves x 4 x 16 = kMixTN)
+// The four waves tile the work group's kMixTM x kMixTN block as kWR x kWC:
+// wave (wr, wc) owns rows wr kMixTM/kWR .. + kMixTM/kWR (kRB 16-row
+// blocks) and the column blocks cb = wc, wc + kWC, ... (kCB of them).
+constexpr int kWR = 2, kWC = 2;
+constexpr int kRB = kMixTM / (16 * kWR);
+constexpr int kCB = kMixTN / (16 * kWC);
+constexpr int kCBH = kCB / 2;      // column blocks per operand load
 
 __device__ __forceinline__ float ker_value(int k, int off, int ph, int nup, const float *__restrict__ taps) {
     if (ph == 0) return k == off + nup ? 1.0f : 0.0f;
@@ -51,40 +57,61 @@ __device__ __forceinline__ float ker_value(int k, int off, int ph, int nup, cons
 }
 
 struct UpArgs {
-    const float *prev;       // level j+1 buffer, row stride S
-    int S, n_prev, m0;       // m0: buffer index of the window start
+    const float *prev;       // level j+1 buffer of this wave's rows, row stride kMixS
+    int n_prev, m0;          // m0: buffer index of the window start
     int off, ph, nup;
     const float *taps;       // sub-kernels of this stage, [p][kUpTaps]
 };
 
+// Per slice, a wave addresses W~ and its basis-output ring through buffer
+// resources: per-lane byte offsets (row of W~, ring position of each of its
+// column blocks, plus the lane group's K offset) are fixed for the slice and
+// the step over basis rows is a scalar offset.
+//
 // ------------------------------------------------------------------ FP32
 // 16 basis rows per step as four 16x16x4 MFMAs; lane group g supplies basis
 // rows l0 + 4g .. l0 + 4g + 3, one per MFMA, on both sides.
 struct MixF32 {
     static constexpr int K = 16;
-    struct A {
-        float4 w[kRB];
+    struct Src {
+        __amdgpu_buffer_rsrc_t w, y;
+        int va[kRB], vb[kCB];
     };
-    struct B {
-        float4 y;
+    struct FragA {
+        float4 a[kRB];
     };
-    static __device__ __forceinline__ void load_a(A &a, const MixSlice &ms, int r0, int l0, int li, int lg) {
+    struct FragB {
+        float4 b[kCBH];
+    };
+    static __device__ __forceinline__ void init(Src &s, const MixSlice &ms, const void *ring, int r0, const int (&p)[kCB],
+                                                int li, int lg) {
+        s.w = buffer_rsrc(ms.W, (uint32_t)ms.rows_pad * ms.Lpad * 4);   // r0: first row of this wave
+        s.y = buffer_rsrc(ring, (uint32_t)(2 * ms.capY) * ms.Lpad * 4);
 #pragma unroll
-        for (int m = 0; m < kRB; ++m)
-            a.w[m] = *reinterpret_cast<const float4 *>(ms.W + (int64_t)(r0 + 16 * m + li) * ms.Lpad + l0 + 4 * lg);
-    }
-    static __device__ __forceinline__ void load_b(B &b, const void *ring, const MixSlice &ms, int p, int l0,
-                                                  int lg) {
-        b.y = *reinterpret_cast<const float4 *>(static_cast<const float *>(ring) + (int64_t)p * ms.Lpad + l0 +
-                                                 4 * lg);
-    }
-    static __device__ __forceinline__ void mma(floatx4 (&acc)[kRB], const A &a, const B &b) {
+        for (int m = 0; m < kRB; ++m) s.va[m] = ((r0 + 16 * m + li) * ms.Lpad + 4 * lg) * 4;
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) {
-            acc[m] = mfma_16x16x4_f32(a.w[m].x, b.y.x, acc[m]);
-            acc[m] = mfma_16x16x4_f32(a.w[m].y, b.y.y, acc[m]);
-            acc[m] = mfma_16x16x4_f32(a.w[m].z, b.y.z, acc[m]);
-            acc[m] = mfma_16x16x4_f32(a.w[m].w, b.y.w, acc[m]);
+        for (int i = 0; i < kCB; ++i) s.vb[i] = (p[i] * ms.Lpad + 4 * lg) * 4;
+    }
+    static __device__ __forceinline__ void load_a(FragA &f, const Src &s, int l0) {
+#pragma unroll
+        for (int m = 0; m < kRB; ++m) f.a[m] = buffer_load16<float4>(s.w, s.va[m], l0 * 4);
+    }
+    static __device__ __forceinline__ void load_b(FragB &f, const Src &s, int l0, int i0) {
+#pragma unroll
+        for (int i = 0; i < kCBH; ++i) f.b[i] = buffer_load16<float4>(s.y, s.vb[i0 + i], l0 * 4);
+    }
+    static __device__ __forceinline__ void mma(floatx4 (&acc)[kCB][kRB], const FragA &a, const FragB &f, int i0,
+                                               int ncb) {
+#pragma unroll
+        for (int i = 0; i < kCBH; ++i) {
+            if (i0 + i >= ncb) continue;
+#pragma unroll
+            for (int m = 0; m < kRB; ++m) {
+                acc[i0 + i][m] = mfma_16x16x4_f32(a.a[m].x, f.b[i].x, acc[i0 + i][m]);
+                acc[i0 + i][m] = mfma_16x16x4_f32(a.a[m].y, f.b[i].y, acc[i0 + i][m]);
+                acc[i0 + i][m] = mfma_16x16x4_f32(a.a[m].z, f.b[i].z, acc[i0 + i][m]);
+                acc[i0 + i][m] = mfma_16x16x4_f32(a.a[m].w, f.b[i].w, acc[i0 + i][m]);
+            }
         }
     }
     // 24-wide window, six K-steps of 4
@@ -95,7 +122,7 @@ struct MixF32 {
             const float b = ker_value(kk, u.off, u.ph, u.nup, u.taps);
             const int idx = min(u.m0 + kk, u.n_prev - 1);
 #pragma unroll
-            for (int m = 0; m < kRB; ++m) acc[m] = mfma_16x16x4_f32(u.prev[(16 * m + li) * u.S + idx], b, acc[m]);
+            for (int m = 0; m < kRB; ++m) acc[m] = mfma_16x16x4_f32(u.prev[(16 * m + li) * kMixS + idx], b, acc[m]);
         }
     }
 };
@@ -107,34 +134,54 @@ struct MixF32 {
 template <typename T, typename T8, bool SPLIT_W>
 struct Mix16 {
     static constexpr int K = 32;
-    struct A {
-        T8 h[kRB];
-        T8 l[SPLIT_W ? kRB : 1];
+    struct Src {
+        __amdgpu_buffer_rsrc_t wh, wl, y;
+        int ylo;                 // byte offset of the ring's lo plane
+        int va[kRB], vb[kCB];
     };
-    struct B {
-        T8 h, l;
+    struct FragA {
+        T8 h[kRB], l[SPLIT_W ? kRB : 1];
     };
-    static __device__ __forceinline__ void load_a(A &a, const MixSlice &ms, int r0, int l0, int li, int lg) {
+    struct FragB {
+        T8 h[kCBH], l[kCBH];
+    };
+    static __device__ __forceinline__ void init(Src &s, const MixSlice &ms, const void *ring, int r0, const int (&p)[kCB],
+                                                int li, int lg) {
+        const uint32_t wbytes = (uint32_t)ms.rows_pad * ms.Lpad * 2;
+        s.wh = buffer_rsrc(ms.Whi, wbytes);
+        if constexpr (SPLIT_W) s.wl = buffer_rsrc(ms.Wlo, wbytes);
+        s.ylo = 2 * ms.capY * ms.Lpad * 2;
+        s.y = buffer_rsrc(ring, 2u * s.ylo);
+#pragma unroll
+        for (int m = 0; m < kRB; ++m) s.va[m] = ((r0 + 16 * m + li) * ms.Lpad + 8 * lg) * 2;
+#pragma unroll
+        for (int i = 0; i < kCB; ++i) s.vb[i] = (p[i] * ms.Lpad + 8 * lg) * 2;
+    }
+    static __device__ __forceinline__ void load_a(FragA &f, const Src &s, int l0) {
 #pragma unroll
         for (int m = 0; m < kRB; ++m) {
-            const int64_t o = (int64_t)(r0 + 16 * m + li) * ms.Lpad + l0 + 8 * lg;
-            a.h[m] = *reinterpret_cast<const T8 *>(static_cast<const T *>(ms.Whi) + o);
-            if constexpr (SPLIT_W) a.l[m] = *reinterpret_cast<const T8 *>(static_cast<const T *>(ms.Wlo) + o);
+            f.h[m] = buffer_load16<T8>(s.wh, s.va[m], l0 * 2);
+            if constexpr (SPLIT_W) f.l[m] = buffer_load16<T8>(s.wl, s.va[m], l0 * 2);
         }
     }
-    static __device__ __forceinline__ void load_b(B &b, const void *ring, const MixSlice &ms, int p, int l0,
-                                                  int lg) {
-        const T *hi = static_cast<const T *>(ring);
-        const int64_t o = (int64_t)p * ms.Lpad + l0 + 8 * lg;
-        b.h = *reinterpret_cast<const T8 *>(hi + o);
-        b.l = *reinterpret_cast<const T8 *>(hi + 2LL * ms.capY * ms.Lpad + o);
-    }
-    static __device__ __forceinline__ void mma(floatx4 (&acc)[kRB], const A &a, const B &b) {
+    static __device__ __forceinline__ void load_b(FragB &f, const Src &s, int l0, int i0) {
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) {
-            acc[m] = mfma16(a.h[m], b.l, acc[m]);
-            if constexpr (SPLIT_W) acc[m] = mfma16(a.l[m], b.h, acc[m]);
-            acc[m] = mfma16(a.h[m], b.h, acc[m]);
+        for (int i = 0; i < kCBH; ++i) {
+            f.h[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * 2);
+            f.l[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * 2 + s.ylo);
+        }
+    }
+    static __device__ __forceinline__ void mma(floatx4 (&acc)[kCB][kRB], const FragA &a, const FragB &f, int i0,
+                                               int ncb) {
+#pragma unroll
+        for (int i = 0; i < kCBH; ++i) {
+            if (i0 + i >= ncb) continue;
+#pragma unroll
+            for (int m = 0; m < kRB; ++m) {
+                acc[i0 + i][m] = mfma16(a.h[m], f.l[i], acc[i0 + i][m]);
+                if constexpr (SPLIT_W) acc[i0 + i][m] = mfma16(a.l[m], f.h[i], acc[i0 + i][m]);
+                acc[i0 + i][m] = mfma16(a.h[m], f.h[i], acc[i0 + i][m]);
+            }
         }
     }
     // 32-wide window, one K-step; both operands split (three products), so
@@ -154,7 +201,7 @@ struct Mix16 {
 #pragma unroll
             for (int j = 0; j < 8; ++j) {
                 const int idx = min(u.m0 + 8 * lg + j, u.n_prev - 1);
-                const float pv = u.prev[(16 * m + li) * u.S + idx];
+                const float pv = u.prev[(16 * m + li) * kMixS + idx];
                 const T h = (T)pv;
                 ph[j] = h;
                 pl[j] = (T)(pv - (float)h);
@@ -168,26 +215,32 @@ struct Mix16 {
 
 // ------------------------------------------------------------------ kernel
 template <typename Op>
-__global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ items, const MixBank *__restrict__ banks,
+__global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__ items, const MixBank *__restrict__ banks,
                                                   const MixSlice *__restrict__ slices,
                                                   const float *__restrict__ uptaps, float *__restrict__ series,
                                                   PartialPeak *__restrict__ partials, int32_t F, int32_t S,
                                                   int32_t nup, int32_t n_items, int32_t group,
                                                   const int64_t *__restrict__ stride_ctr) {
-    extern __shared__ float lvl[];   // [kMixTM][S]: one level of the chain
-    __shared__ PeakCand wbest[4][kMixTM / 2];
+    extern __shared__ float lvl[];   // [kMixTM][kMixS]: one level of the chain, then the bank's taps
+    __shared__ PeakCand wbest[4][8 * kRB];
     const int item = xcd_item(group);
     if (item >= n_items) return;
     const MixItem it = items[item];
     const MixBank &B = banks[it.bank];
     // ring positions are taken modulo capY, a power of two dividing 2^32
     const uint32_t kstr = (uint32_t)*stride_ctr;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform: scalar branches below
+    const int wr = wave / kWC, wc = wave % kWC;
+    const int rw = wr * (kMixTM / kWR);   // first row of this wave within the tile
     const int li = lane & 15, lg = lane >> 4;
-
-    PeakCand best[2 * kRB];
-#pragma unroll
-    for (int t = 0; t < 2 * kRB; ++t) best[t] = PeakCand{-1.0f, 0x7fffffff, 0.f, 0.f};
+    // the polyphase sub-kernels of every stage of the bank, read by the
+    // upsampling (first used after the lowest level's barriers)
+    float *tp = lvl + kMixTM * kMixS;
+    for (int j = 1; j < B.nlev; ++j) {
+        const float *src = uptaps + (B.p[j] - 1) * kUpTaps;
+        for (int e = tid; e < B.p[j] * kUpTaps; e += 256) tp[B.up_off[j] + e] = src[e];
+    }
 
     int lo_prev = 0;
     for (int j = B.nlev - 1; j >= 0; --j) {
@@ -200,99 +253,112 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ it
 #pragma unroll
             for (int m = 0; m < kRB; ++m) acc[i][m] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+        // this wave's column blocks cb = wc + kWC i, i < ncb
+        const int ncb = min(kCB, max(0, (nb - wc + kWC - 1) / kWC));
         for (int s = B.slice_begin[j]; s < B.slice_begin[j + 1]; ++s) {
             const MixSlice &ms = slices[s];
             const uint32_t pos0 = (kstr * (uint32_t)B.rate[j] + (uint32_t)lo) & (uint32_t)(ms.capY - 1);
             const void *ring = static_cast<const char *>(ms.Y) + (int64_t)it.det * ms.ydet * 4;
             // columns past the window read its last sample (finite, never
             // stored); the window (n <= capY, checked at plan time) is
-            // contiguous in the mirror ring, the mask only guards the address
+            // contiguous in the mirror ring, and the buffer range guards the rest
             int pc[kCB];
 #pragma unroll
-            for (int i = 0; i < kCB; ++i)
-                pc[i] = (int)((pos0 + (uint32_t)min((wave + 4 * i) * 16 + li, n - 1)) & (uint32_t)(2 * ms.capY - 1));
+            for (int i = 0; i < kCB; ++i) pc[i] = (int)pos0 + min((wc + kWC * i) * 16 + li, n - 1);
+            typename Op::Src src;
+            Op::init(src, ms, ring, it.r0 + rw, pc, li, lg);
+            // loads are unconditional: idle column blocks re-read the
+            // window's last sample (L1 hits)
             for (int l0 = 0; l0 < ms.Lpad; l0 += Op::K) {
-                typename Op::A a;
-                typename Op::B b[kCB];
-                Op::load_a(a, ms, it.r0, l0, li, lg);
-#pragma unroll
-                for (int i = 0; i < kCB; ++i)
-                    if (wave + 4 * i < nb) Op::load_b(b[i], ring, ms, pc[i], l0, lg);
-#pragma unroll
-                for (int i = 0; i < kCB; ++i)
-                    if (wave + 4 * i < nb) Op::mma(acc[i], a, b[i]);
+                typename Op::FragA a;
+                typename Op::FragB b;
+                Op::load_a(a, src, l0);
+                Op::load_b(b, src, l0, 0);
+                Op::mma(acc, a, b, 0, ncb);
+                if (ncb > kCBH) {
+                    Op::load_b(b, src, l0, kCBH);
+                    Op::mma(acc, a, b, kCBH, ncb);
+                }
             }
         }
         if (j < B.nlev - 1) {
             const int logp = B.shp[j + 1];
-            const float *taps = uptaps + (B.p[j + 1] - 1) * kUpTaps;
+            const float *taps = tp + B.up_off[j + 1];
             const int n_prev = B.n[j + 1];
 #pragma unroll
             for (int i = 0; i < kCB; ++i) {
-                const int cb = wave + 4 * i;
+                const int cb = wc + kWC * i;
                 if (cb >= nb) continue;   // wave-uniform
                 const int i0 = lo + cb * 16;
                 const int q0 = i0 >> logp;   // arithmetic shift: floor for negative indices
                 const int ii = i0 + li;
-                const UpArgs ua{lvl, S, n_prev, q0 - nup - lo_prev, (ii >> logp) - q0, ii & ((1 << logp) - 1), nup,
-                                taps};
+                const UpArgs ua{lvl + rw * kMixS, n_prev, q0 - nup - lo_prev, (ii >> logp) - q0,
+                                ii & ((1 << logp) - 1), nup, taps};
                 Op::upsample(ua, li, lg, acc[i]);
+                __builtin_amdgcn_sched_barrier(0);   // keep one block's LDS reads in flight at a time
             }
         }
         __syncthreads();   // every wave is done reading level j+1
+        if (j > 0) {
 #pragma unroll
-        for (int i = 0; i < kCB; ++i) {
-            const int cb = wave + 4 * i;
-            if (cb >= nb) continue;
-            const int c = cb * 16 + li;
-            if (c >= n) continue;
-            if (j > 0) {
+            for (int i = 0; i < kCB; ++i) {
+                const int cb = wc + kWC * i;
+                if (cb >= nb) continue;
+                const int c = cb * 16 + li;
+                if (c >= n) continue;
 #pragma unroll
                 for (int m = 0; m < kRB; ++m)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) lvl[(16 * m + 4 * lg + v) * S + c] = acc[i][m][v];
-            } else {
-                const int t = it.t0 + c;
+                    for (int v = 0; v < 4; ++v) lvl[(rw + 16 * m + 4 * lg + v) * kMixS + c] = acc[i][m][v];
+            }
+            __syncthreads();   // level j complete before it is read as prev
+            lo_prev = lo;
+            continue;
+        }
+        // level 0: SNR series and trigger candidates.  Lane (li, lg) holds
+        // templates t8 + 8 m + h, t8 = (r0 + rw)/2 + 2 lg, at the samples
+        // t0 + cb 16 + li; one template's candidate is live at a time.
+        const int t8 = (it.r0 + rw) / 2 + 2 * lg;
+        float2 *orow = series ? reinterpret_cast<float2 *>(series + B.series_off) +
+                                    ((int64_t)it.det * B.M + t8) * F + it.t0 + li
+                              : nullptr;
 #pragma unroll
-                for (int m = 0; m < kRB; ++m) {
+        for (int m = 0; m < kRB; ++m) {
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        const float re = acc[i][m][2 * h], im = acc[i][m][2 * h + 1];
-                        const int tmpl = it.r0 / 2 + 8 * m + 2 * lg + h;
-                        if (series && tmpl < B.M) {
-                            float2 *o = reinterpret_cast<float2 *>(series + B.series_off) +
-                                        ((int64_t)it.det * B.M + tmpl) * F + t;
-                            *o = make_float2(re, im);
-                        }
-                        const float p2 = re * re + im * im;
-                        if (better(p2, t, best[2 * m + h].p2, best[2 * m + h].idx))
-                            best[2 * m + h] = PeakCand{p2, t, re, im};
-                    }
+            for (int h = 0; h < 2; ++h) {
+                const bool live = t8 + 8 * m + h < B.M;
+                PeakCand b{-1.0f, 0x7fffffff, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < kCB; ++i) {
+                    const int cb = wc + kWC * i;
+                    if (cb >= nb) continue;
+                    const int c = cb * 16 + li;
+                    if (c >= n) continue;
+                    const float re = acc[i][m][2 * h], im = acc[i][m][2 * h + 1];
+                    if (orow && live) orow[(int64_t)(8 * m + h) * F + cb * 16] = make_float2(re, im);
+                    const float p2 = re * re + im * im;
+                    if (better(p2, it.t0 + c, b.p2, b.idx)) b = PeakCand{p2, it.t0 + c, re, im};
                 }
+                // reduce over the 16 lanes of the row group
+                for (int off = 1; off < 16; off <<= 1) {
+                    PeakCand o;
+                    o.p2 = __shfl_xor(b.p2, off, 64);
+                    o.idx = __shfl_xor(b.idx, off, 64);
+                    o.re = __shfl_xor(b.re, off, 64);
+                    o.im = __shfl_xor(b.im, off, 64);
+                    if (better(o.p2, o.idx, b.p2, b.idx)) b = o;
+                }
+                if (li == 0) wbest[wave][8 * m + 2 * lg + h] = b;
             }
         }
-        __syncthreads();   // level j complete before it is read as prev
-        lo_prev = lo;
-    }
-    // trigger candidates: reduce over the 16 lanes of a row group, then waves
-#pragma unroll
-    for (int q = 0; q < 2 * kRB; ++q) {
-        PeakCand b = best[q];
-        for (int off = 1; off < 16; off <<= 1) {
-            PeakCand o;
-            o.p2 = __shfl_xor(b.p2, off, 64);
-            o.idx = __shfl_xor(b.idx, off, 64);
-            o.re = __shfl_xor(b.re, off, 64);
-            o.im = __shfl_xor(b.im, off, 64);
-            if (better(o.p2, o.idx, b.p2, b.idx)) b = o;
-        }
-        if (li == 0) wbest[wave][(q >> 1) * 8 + lg * 2 + (q & 1)] = b;
     }
     __syncthreads();
+    // the kWC waves of a row group hold candidates of the same templates
     if (tid < kMixTM / 2) {
-        PeakCand b = wbest[0][tid];
-        for (int w = 1; w < 4; ++w) {
-            const PeakCand o = wbest[w][tid];
+        const int g = tid / (8 * kRB), tl = tid % (8 * kRB);
+        PeakCand b = wbest[g * kWC][tl];
+        for (int w = 1; w < kWC; ++w) {
+            const PeakCand o = wbest[g * kWC + w][tl];
             if (better(o.p2, o.idx, b.p2, b.idx)) b = o;
         }
         const int tmpl = it.r0 / 2 + tid;
@@ -303,9 +369,9 @@ __global__ __launch_bounds__(256) void mix_kernel(const MixItem *__restrict__ it
     }
 }
 
-size_t mix_lds(int precision, int S) {
-    if (precision < LLOID_FP32 || precision > LLOID_FP8_BF16) return 0;
-    return (size_t)kMixTM * S * sizeof(float);
+size_t mix_lds(int precision, int S, int TP) {
+    if (precision < LLOID_FP32 || precision > LLOID_FP8_BF16 || S != kMixS) return 0;
+    return (size_t)(kMixTM * kMixS + TP) * sizeof(float);
 }
 
 hipError_t configure_down_lds(size_t down_bytes);
@@ -328,12 +394,11 @@ hipError_t configure_lds(int precision, size_t mix_bytes, size_t down_bytes) {
 
 hipError_t launch_mix(const LaunchCtx &ctx, int precision, const MixItem *items, int32_t n_items,
                       const MixBank *banks, const MixSlice *slices, const float *uptaps, float *series,
-                      PartialPeak *partials, int32_t F, int32_t n_det, int32_t S, int32_t SW, int32_t nup,
+                      PartialPeak *partials, int32_t F, int32_t n_det, int32_t S, int32_t TP, int32_t nup,
                       int32_t group) {
     (void)n_det;
-    (void)SW;
     if (n_items == 0) return hipSuccess;
-    const size_t lds = mix_lds(precision, S);
+    const size_t lds = mix_lds(precision, S, TP);
     const dim3 grid(xcd_grid(n_items, group));
     switch (precision) {
         case LLOID_FP32:

@@ -100,7 +100,7 @@ struct lloid_plan {
     int n_mix = 0;
     MixBank *d_mbanks = nullptr;
     MixSlice *d_mslices = nullptr;
-    int mixS = 0, mixSW = 0;
+    int mixS = 0, mixTP = 0;   // mix level-buffer row stride, upsampling taps in LDS
     PeakItem *d_peakitems = nullptr;
     int n_peakitems = 0;
     PartialPeak *d_partials = nullptr;
@@ -212,7 +212,8 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
             for (int sp = 0; sp < s.nsplit; ++sp) {
                 const int k0 = sp * P->ksplit;
                 const int klen = std::min(P->ksplit, s.Npad - k0);
-                for (int c0 = 0; c0 < f; c0 += kCorrTQ) {
+                for (int c0 = 0; c0 < f; c0 += kCorrTQ)
+                for (int r0 = 0; r0 < s.Lpad; r0 += kCorrMB * 16) {
                     CorrItem it{};
                     it.U = s.U32;
                     it.Uhi = s.Uhi;
@@ -229,7 +230,8 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
                     it.ncols = std::min(kCorrTQ, f - c0);
                     it.k0 = k0;
                     it.klen = klen;
-                    it.mb = s.Lpad / 16;
+                    it.mb = std::min(kCorrMB, (s.Lpad - r0) / 16);
+                    it.r0 = r0;
                     items.push_back(it);
                 }
             }
@@ -567,13 +569,14 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         std::vector<MixSlice> ms;
         std::vector<MixItem> items;
         std::vector<PeakItem> pk;
-        int S = 0, SW = 0;
+        int S = 0, TP = 0;
         for (int b = 0; b < n_banks; ++b) {
             PBank &pb = P->banks[b];
             MixBank m{};
             m.M = pb.M;
             m.nlev = pb.nlev;
             int64_t lo = 0, hi = kMixTN;
+            int tp = 0;   // floats of this bank's upsampling sub-kernels
             for (int j = 0; j < pb.nlev; ++j) {
                 m.rate[j] = pb.rates[j];
                 m.P[j] = F / pb.rates[j];
@@ -582,6 +585,8 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                     const int p = pb.rates[j - 1] / pb.rates[j];
                     m.p[j] = p;
                     m.shp[j] = ilog2(p);
+                    m.up_off[j] = tp;
+                    tp += p * kUpTaps;
                     lo = floordiv(lo, p) - nup;
                     hi = floordiv(hi - 1, p) + nup + 1;
                     S = std::max<int>(S, (int)(hi - lo));
@@ -590,7 +595,6 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                 m.lo[j] = (int)lo;
                 m.n[j] = (int)(hi - lo);
             }
-            int lvl_l[kMaxLevels] = {0};
             int cursor = (int)ms.size();
             for (int j = 0; j <= pb.nlev; ++j) m.slice_begin[j] = cursor;
             for (int j = 0; j < pb.nlev; ++j) {
@@ -599,12 +603,11 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                     PSlice &s = P->slices[id];
                     if (s.level != j) continue;
                     if (m.n[j] > s.capY) return LLOID_E_UNSUPPORTED;   // a tile's window must fit the ring
-                    ms.push_back(MixSlice{s.W32, s.Whi, s.Wlo, s.yring, s.ydet, s.L, s.Lpad, s.capY, s.level});
-                    lvl_l[j] += s.Lpad;
+                    ms.push_back(MixSlice{s.W32, s.Whi, s.Wlo, s.yring, s.ydet, s.L, s.Lpad, s.capY, s.level, pb.rows_pad, 0});
                 }
             }
             m.slice_begin[pb.nlev] = (int)ms.size();
-            for (int j = 0; j < pb.nlev; ++j) SW = std::max(SW, lvl_l[j]);
+            TP = std::max(TP, tp);
             m.series_off = pb.series_off;
             m.peak_off = pb.peak_off;
             m.part_off = pb.part_off;
@@ -628,13 +631,10 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         // mod 32 words (the upsample's 16 rows x 2 columns per half-wave hit
         // distinct banks); every window must fit one 256-thread row load
         if (S > kMixTN) return LLOID_E_UNSUPPORTED;
-        {
-            int s2 = std::max(S, 1);
-            while (s2 % 32 != 2 && s2 % 32 != 18) ++s2;
-            P->mixS = s2;
-        }
-        P->mixSW = SW;
-        const size_t mix_lds = mix_lds_bytes(P->precision, P->mixS);
+        if (S > kMixS) return LLOID_E_UNSUPPORTED;
+        P->mixS = kMixS;
+        P->mixTP = TP;
+        const size_t mix_lds = mix_lds_bytes(P->precision, P->mixS, P->mixTP);
         if (mix_lds == 0 || mix_lds > (size_t)kMaxLdsBytes) return LLOID_E_UNSUPPORTED;
         HIP_OK(configure_lds(P->precision, mix_lds, (size_t)P->down_lds * 4));
         P->n_mix = (int)items.size();
@@ -790,7 +790,7 @@ static lloid_status enqueue_stride(lloid_plan *P, hipStream_t st, const float *s
     HIP_OK(P->mark(LLOID_K_REDUCE, st, false));
     HIP_OK(P->mark(LLOID_K_MIX, st, true));
     HIP_OK(launch_mix(ctx, P->precision, P->d_mix, P->n_mix, P->d_mbanks, P->d_mslices, P->d_uptaps, snr,
-                      P->d_partials, P->F, P->n_det, P->mixS, P->mixSW, P->nup, P->mix_group));
+                      P->d_partials, P->F, P->n_det, P->mixS, P->mixTP, P->nup, P->mix_group));
     HIP_OK(P->mark(LLOID_K_MIX, st, false));
     HIP_OK(P->mark(LLOID_K_PEAKS, st, true));
     HIP_OK(launch_peaks(ctx, P->d_peakitems, P->n_peakitems, P->d_partials, peaks, P->cfg.snr_threshold,
@@ -964,6 +964,9 @@ lloid_status lloid_inspect(lloid_plan *P, int32_t what, int32_t index, int32_t d
 namespace {
 constexpr int64_t kGradSplitW = 16384;   // K split of dW = 2 G Y^T (K = time)
 constexpr int64_t kGradSplitU = 8192;    // K split of dU (K = time)
+// zero tail of the gradient's linear strain segments: the correlation reads
+// up to kCorrTQ + 64 samples past a window start
+constexpr int64_t kSegPad = kCorrTQ + 64;
 constexpr int kLossBlocks = 64;
 
 int64_t seg_lo(const PBank &b, int j, int nup) {
@@ -1036,7 +1039,7 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
     for (auto &kv : dlo) {
         const int D = kv.first;
         dlen[D] = TF / D - kv.second + 256;
-        ST_OK(get(&dseg[D], (size_t)ND * (dlen[D] + 128), true));
+        ST_OK(get(&dseg[D], (size_t)ND * (dlen[D] + kSegPad), true));
     }
 
     // ---- forward with capture
@@ -1065,7 +1068,7 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
             const int64_t a = D == 1 ? (int64_t)k * F : (int64_t)k * f - P->ndown;
             for (int d = 0; d < ND; ++d)
                 HIP_OK(launch_copy_window(st, r.base + d * r.det_stride, 0, r.cap, a, f, 1,
-                                          kv.second + d * (dlen[D] + 128), 0, a - dlo[D]));
+                                          kv.second + d * (dlen[D] + kSegPad), 0, a - dlo[D]));
         }
     }
     P->stride = T;
@@ -1093,7 +1096,8 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
     CorrItem *d_items = nullptr;
     int64_t max_items = 1;
     for (int i = 0; i < ns; ++i)
-        max_items = std::max(max_items, ((P->slices[i].N + kCorrTQ - 1) / kCorrTQ) * (qld[i] / kGradSplitU + 1));
+        max_items = std::max(max_items, ((P->slices[i].N + kCorrTQ - 1) / kCorrTQ) * (qld[i] / kGradSplitU + 1) *
+                                            ((P->slices[i].Lpad + kCorrMB * 16 - 1) / (kCorrMB * 16)));
     ST_OK(get(&d_items, (size_t)max_items, false));
 
     std::vector<int64_t> offW(ns), offU(ns);
@@ -1140,10 +1144,11 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
                     std::vector<CorrItem> items;
                     const int64_t nsu = (qld[i] + kGradSplitU - 1) / kGradSplitU;
                     for (int64_t sp = 0; sp < nsu; ++sp)
-                        for (int c0 = 0; c0 < s.N; c0 += kCorrTQ) {
+                        for (int c0 = 0; c0 < s.N; c0 += kCorrTQ)
+                        for (int r0 = 0; r0 < s.Lpad; r0 += kCorrMB * 16) {
                             CorrItem it{};
                             it.U = dy;
-                            it.ring = dseg[s.D] + d * (dlen[s.D] + 128);
+                            it.ring = dseg[s.D] + d * (dlen[s.D] + kSegPad);
                             it.part = part + sp * s.Lpad * s.N;
                             it.off = glo - s.delay - (s.N - 1) - dlo[s.D];
                             it.Npad = (int32_t)qld[i];
@@ -1154,7 +1159,8 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
                             it.ncols = std::min(kCorrTQ, s.N - c0);
                             it.k0 = (int32_t)(sp * kGradSplitU);
                             it.klen = (int32_t)std::min<int64_t>(kGradSplitU, qld[i] - sp * kGradSplitU);
-                            it.mb = s.Lpad / 16;
+                            it.mb = std::min(kCorrMB, (s.Lpad - r0) / 16);
+                            it.r0 = r0;
                             items.push_back(it);
                         }
                     HIP_OK(hipMemcpyAsync(d_items, items.data(), sizeof(CorrItem) * items.size(),

@@ -54,3 +54,26 @@ def test_realistic_bank_reduced_precision(plan_cls, precision):
     print(f"realistic bank {precision}: eps={eps:.3e} rel_rms={rms:.3e}")
     assert eps <= EXPECT[precision]
     check_peaks(pk[0], ref, F, float(np.abs(z[0] - ref).max()))
+
+
+@pytest.mark.parametrize("precision", ["bf16x3", "fp16"])
+def test_split_basis_output_rings(plan_cls, precision):
+    """The 16-bit forms keep the basis outputs as hi + lo planes of a
+    time-major ring; read back through lloid_inspect they match the
+    oracle's correlate step to the form's precision."""
+    from oracle import lloid as O
+    w = synth.config1()
+    x = synth.workload_strain(w)
+    F = w.sample_rate
+    plan = plan_cls(w.banks, F, 1, precision)
+    run_gpu(plan, x, 5, 1)
+    k, f = 6, 512
+    s = w.banks[0].slices[1]
+    la = plan.query(9, 1)
+    q_lo, q_hi = k * f + la - 400, k * f + la
+    y_gpu = plan.basis_out(1, s.n_basis, 0, q_lo, q_hi)
+    dd = O.downsample(x[0], 4, q_lo - s.delay - s.n_taps + 1, q_hi - s.delay)
+    y_ref = O.correlate(s.basis, dd, q_lo - s.delay - s.n_taps + 1, s.delay, q_lo, q_hi)
+    err = np.abs(y_gpu - y_ref).max() / np.abs(y_ref).max()
+    print(f"{precision} basis outputs: rel err {err:.3e}")
+    assert err < EXPECT[precision]
