@@ -53,12 +53,13 @@ struct CorrItem {
     int32_t r0;              // first basis row of this item
 };
 
-// Deterministic split-K reduction of 64 new columns of one slice and
-// detector into its basis-output ring (time-major, see MixSlice).
+// Deterministic split-K reduction of 64 new columns x 32 basis rows
+// [l0, l0 + 32) of one slice and detector into its basis-output ring
+// (time-major, see MixSlice).
 struct ReduceItem {
     const float *part;       // [nsplit][Lpad][f]
     void *yring;             // ring of this detector
-    int32_t nsplit, L, Lpad, f, capY, la, c0, pad_;
+    int32_t nsplit, L, Lpad, f, capY, la, c0, l0;
 };
 
 // Decimation (Eq. (sinc) kernel, zero phase): d_D[m] = sum_t g[t] x[D m + t - c]

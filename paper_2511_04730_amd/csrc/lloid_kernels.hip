@@ -89,23 +89,23 @@ hipError_t launch_down(const LaunchCtx &ctx, const DownItem *items, int32_t n_it
     return hipGetLastError();
 }
 
-// Sum the split partials of 64 new columns in a fixed order (split 0
-// first), transpose through LDS and append them to the time-major ring:
-// one row of Lpad outputs per sample, rows L .. Lpad-1 zero.  16-bit forms
-// store y as hi = T(y) and lo = T(y - hi) in two planes.
+// Sum the split partials of 64 new columns x 32 basis rows in a fixed
+// order (split 0 first), transpose through LDS and append them to the
+// time-major ring: one row of Lpad outputs per sample, rows L .. Lpad-1
+// zero.  16-bit forms store y as hi = T(y) and lo = T(y - hi) in two planes.
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceItem *__restrict__ items,
                                                      const int64_t *__restrict__ stride_ctr) {
-    __shared__ float sm[kMaxBasis][65];
+    __shared__ float sm[32][65];
     const ReduceItem it = items[blockIdx.x];
     const int64_t k = *stride_ctr;
     const int ncols = min(64, it.f - it.c0);
     const int64_t plane = (int64_t)it.Lpad * it.f;
-    for (int e = threadIdx.x; e < it.L * 64; e += 256) {
+    for (int e = threadIdx.x; e < 32 * 64; e += 256) {
         const int l = e >> 6, c = e & 63;
         float s = 0.0f;
-        if (c < ncols) {
-            const float *p = it.part + (int64_t)l * it.f + it.c0 + c;
+        if (c < ncols && it.l0 + l < it.L) {
+            const float *p = it.part + (int64_t)(it.l0 + l) * it.f + it.c0 + c;
             for (int sp = 0; sp < it.nsplit; ++sp) s += p[sp * plane];
         }
         sm[l][c] = s;
@@ -114,34 +114,33 @@ __global__ __launch_bounds__(256) void reduce_kernel(const ReduceItem *__restric
     const int64_t q0 = k * it.f + it.la + it.c0;
     const int64_t mask = it.capY - 1;
     constexpr int V = sizeof(T) == 4 ? 4 : 8;   // outputs per thread and row: 16 bytes
-    const int groups = it.Lpad / V;
+    const int nrow = min(32, it.Lpad - it.l0);
+    const int groups = nrow / V;
     for (int e = threadIdx.x; e < ncols * groups; e += 256) {
         const int c = e / groups, l = (e % groups) * V;
         const int64_t pos = (q0 + c) & mask;
+        const int64_t o = pos * it.Lpad + it.l0 + l;
+        const int64_t om = (pos + it.capY) * it.Lpad + it.l0 + l;
         if constexpr (sizeof(T) == 4) {
-            float4 v;
-            v.x = l + 0 < it.L ? sm[l + 0][c] : 0.0f;
-            v.y = l + 1 < it.L ? sm[l + 1][c] : 0.0f;
-            v.z = l + 2 < it.L ? sm[l + 2][c] : 0.0f;
-            v.w = l + 3 < it.L ? sm[l + 3][c] : 0.0f;
+            const float4 v = make_float4(sm[l][c], sm[l + 1][c], sm[l + 2][c], sm[l + 3][c]);
             float *ring = static_cast<float *>(it.yring);
-            *reinterpret_cast<float4 *>(ring + pos * it.Lpad + l) = v;
-            *reinterpret_cast<float4 *>(ring + (pos + it.capY) * it.Lpad + l) = v;
+            *reinterpret_cast<float4 *>(ring + o) = v;
+            *reinterpret_cast<float4 *>(ring + om) = v;
         } else {
             typedef T T8 __attribute__((ext_vector_type(8)));
             T8 h, lo;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const float y = l + i < it.L ? sm[l + i][c] : 0.0f;
+                const float y = sm[l + i][c];
                 h[i] = (T)y;
                 lo[i] = (T)(y - (float)h[i]);
             }
             T *hi_plane = static_cast<T *>(it.yring);
             T *lo_plane = hi_plane + 2LL * it.capY * it.Lpad;
-            *reinterpret_cast<T8 *>(hi_plane + pos * it.Lpad + l) = h;
-            *reinterpret_cast<T8 *>(hi_plane + (pos + it.capY) * it.Lpad + l) = h;
-            *reinterpret_cast<T8 *>(lo_plane + pos * it.Lpad + l) = lo;
-            *reinterpret_cast<T8 *>(lo_plane + (pos + it.capY) * it.Lpad + l) = lo;
+            *reinterpret_cast<T8 *>(hi_plane + o) = h;
+            *reinterpret_cast<T8 *>(hi_plane + om) = h;
+            *reinterpret_cast<T8 *>(lo_plane + o) = lo;
+            *reinterpret_cast<T8 *>(lo_plane + om) = lo;
         }
     }
 }

@@ -119,6 +119,7 @@ struct lloid_plan {
     uint32_t g_gap = 0;
     double flops = 0.0;
     int ksplit = kCorrSplitK;      // taps per correlation work item
+    int corr_cols = kCorrTQ;       // output columns per correlation work item
     int corr_group = 16;           // consecutive correlation items per XCD
     int mix_group = 32;            // consecutive mixing items per XCD
 
@@ -212,7 +213,7 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
             for (int sp = 0; sp < s.nsplit; ++sp) {
                 const int k0 = sp * P->ksplit;
                 const int klen = std::min(P->ksplit, s.Npad - k0);
-                for (int c0 = 0; c0 < f; c0 += kCorrTQ)
+                for (int c0 = 0; c0 < f; c0 += P->corr_cols)
                 for (int r0 = 0; r0 < s.Lpad; r0 += kCorrMB * 16) {
                     CorrItem it{};
                     it.U = s.U32;
@@ -227,7 +228,7 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
                     it.cap = r.cap;
                     it.f = f;
                     it.col0 = c0;
-                    it.ncols = std::min(kCorrTQ, f - c0);
+                    it.ncols = std::min(P->corr_cols, f - c0);
                     it.k0 = k0;
                     it.klen = klen;
                     it.mb = std::min(kCorrMB, (s.Lpad - r0) / 16);
@@ -236,8 +237,9 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
                 }
             }
             for (int c0 = 0; c0 < f; c0 += 64)
-                red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L, s.Lpad, f,
-                                         s.capY, s.la, c0, 0});
+                for (int l0 = 0; l0 < s.Lpad; l0 += 32)
+                    red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L,
+                                             s.Lpad, f, s.capY, s.la, c0, l0});
             P->reduce_rows = std::max(P->reduce_rows, s.L);
         }
     }
@@ -381,16 +383,22 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
     }
     P->series_floats = series_off;
 
-    // Tap split of the correlation: the largest of 8192..512 that still gives
-    // at least 2048 work items (8 per CU); longer splits write fewer partial
-    // planes for the reduction to read back.
+    // Correlation tiling: 256-column items and the longest tap split of
+    // 8192..512 that still gives at least 2048 work items (8 per CU); longer
+    // splits write fewer partial planes for the reduction to read back.
+    // Banks too small for that get 64-column items.
     {
-        P->ksplit = kCorrSplitK;
-        for (int cand = 8192; cand >= kCorrSplitK; cand /= 2) {
+        auto count = [&](int cols, int split) {
             int64_t items = 0;
             for (auto &s : P->slices)
-                items += (int64_t)ND * ((s.rate + kCorrTQ - 1) / kCorrTQ) * ((s.Npad + cand - 1) / cand);
-            if (items >= 2048) {
+                items += (int64_t)ND * ((s.rate + cols - 1) / cols) * ((s.Npad + split - 1) / split) *
+                         ((s.Lpad + kCorrMB * 16 - 1) / (kCorrMB * 16));
+            return items;
+        };
+        P->corr_cols = count(kCorrTQ, kCorrSplitK) >= 2048 ? kCorrTQ : 64;
+        P->ksplit = kCorrSplitK;
+        for (int cand = 8192; cand >= kCorrSplitK; cand /= 2) {
+            if (count(P->corr_cols, cand) >= 2048) {
                 P->ksplit = cand;
                 break;
             }
@@ -679,6 +687,7 @@ lloid_status lloid_plan_query(const lloid_plan *P, int32_t what, int32_t index, 
             case LLOID_OPT_CORR_SPLIT: *value = P->ksplit; return LLOID_OK;
             case LLOID_OPT_CORR_GROUP: *value = P->corr_group; return LLOID_OK;
             case LLOID_OPT_MIX_GROUP: *value = P->mix_group; return LLOID_OK;
+            case LLOID_OPT_CORR_COLS: *value = P->corr_cols; return LLOID_OK;
             default: return LLOID_E_ARG;
         }
     }
@@ -749,6 +758,9 @@ lloid_status lloid_set_option(lloid_plan *P, int32_t option, int64_t value) {
         case LLOID_OPT_CORR_GROUP:
             if (value < 0 || value > 64) return LLOID_E_ARG;
             break;
+        case LLOID_OPT_CORR_COLS:
+            if (value < 64 || value > kCorrTQ || value % 64) return LLOID_E_ARG;
+            break;
         case LLOID_OPT_MIX_GROUP:
             if (value < 0 || value > 256) return LLOID_E_ARG;
             break;
@@ -764,6 +776,11 @@ lloid_status lloid_set_option(lloid_plan *P, int32_t option, int64_t value) {
     if (option == LLOID_OPT_CORR_SPLIT) {
         if (P->ksplit == (int)value) return LLOID_OK;
         P->ksplit = (int)value;
+        return build_corr_tables(P, nullptr);
+    }
+    if (option == LLOID_OPT_CORR_COLS) {
+        if (P->corr_cols == (int)value) return LLOID_OK;
+        P->corr_cols = (int)value;
         return build_corr_tables(P, nullptr);
     }
     if (option == LLOID_OPT_CORR_GROUP) P->corr_group = (int)value;

@@ -1,7 +1,8 @@
 """Tiling options and the autotuner (through the C ABI).
 
-The XCD grouping of work items changes only which work group computes an
-item, so results must be bit-identical across groupings (ragged group counts
+The XCD grouping of work items and the correlation item's column count
+change only which work group computes an output, not its summation order,
+so results must be bit-identical across them (ragged group counts
 included).  The correlation tap split changes the FP32 summation order, so
 every split must stay within the FP32 tolerance of the FP64 oracle, also when
 it is changed between strides."""
@@ -36,18 +37,20 @@ def _peaks_equal(a, b):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-def test_xcd_grouping_is_bit_exact(plan_cls, precision):
+def test_grouping_and_columns_are_bit_exact(plan_cls, precision):
     banks = _ragged_banks()
     x = synth.gaussian_strain(91, 2, 4 * F)
     ref = plan_cls(banks, F, 2, precision)
     ref.set_option("corr_group", 0)
     ref.set_option("mix_group", 0)
     z0, p0 = run_gpu(ref, x, 0, 4)
-    for cg, mg in [(16, 32), (3, 5), (64, 256), (1, 1)]:
+    for cg, mg, cols in [(16, 32, 256), (3, 5, 64), (64, 256, 192), (1, 1, 128)]:
         plan = plan_cls(banks, F, 2, precision)
         plan.set_option("corr_group", cg)
         plan.set_option("mix_group", mg)
+        plan.set_option("corr_cols", cols)
         assert plan.option("corr_group") == cg and plan.option("mix_group") == mg
+        assert plan.option("corr_cols") == cols
         z, p = run_gpu(plan, x, 0, 4)
         for b in range(len(banks)):
             assert np.array_equal(z[b], z0[b]), f"groups {cg},{mg} bank {b}"
@@ -116,7 +119,8 @@ def test_option_values_are_checked(plan_cls):
     from paper_2511_04730_amd._lib import LloidError
     plan = plan_cls(_ragged_banks()[:1], F, 1, "fp32")
     for name, bad in [("corr_split", 0), ("corr_split", 100), ("corr_split", 65600), ("corr_group", -1),
-                      ("corr_group", 65), ("mix_group", 257), ("graph", 2)]:
+                      ("corr_group", 65), ("mix_group", 257), ("graph", 2), ("corr_cols", 0),
+                      ("corr_cols", 100), ("corr_cols", 320)]:
         with pytest.raises(LloidError):
             plan.set_option(name, bad)
     opts = plan.options()
@@ -130,8 +134,9 @@ def test_autotune_keeps_results(plan_cls):
     plan = plan_cls(banks, F, 2, "bf16x3")
     xs = torch.from_numpy(x.astype(np.float32)).cuda()
     strides = [xs[:, k * F:(k + 1) * F].contiguous() for k in range(3)]
-    best = autotune(plan, strides, splits=(256, 1024), corr_groups=(0, 16), mix_groups=(0, 32))
+    best = autotune(plan, strides, cols=(64, 256), splits=(256, 1024), corr_groups=(0, 16), mix_groups=(0, 32))
     assert best["corr_split"] in (256, 1024) and best["corr_group"] in (0, 16) and best["mix_group"] in (0, 32)
+    assert best["corr_cols"] in (64, 256)
     assert plan.options()["corr_split"] == best["corr_split"]
     assert plan.stride == 0
     z, _ = run_gpu(plan, x, 0, 4)
