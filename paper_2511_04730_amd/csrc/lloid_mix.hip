@@ -31,9 +31,10 @@
 //   Ker[k][c] = z_ph[off + 2 N_up - k]  for off <= k <= off + 2 N_up, else 0,
 // and for phase 0 Ker is the unit vector at k = off + N_up (the copy case of
 // Eq. (upsample)).  off <= 7 and 2 N_up <= 16, so a 24- (FP32) or 32-wide
-// (16-bit) window of prev holds every tap.  One LDS buffer holds a level:
-// level j's accumulators stay in registers until every wave has read level
-// j+1, then overwrite it.
+// (16-bit) window of prev holds every tap.  One LDS buffer holds a level
+// (FP32, or hi and lo planes split once when the level is written, so that
+// the 16-bit fragments are aligned vector reads); level j's accumulators
+// stay in registers until every wave has read level j+1, then overwrite it.
 #include <hip/hip_runtime.h>
 
 #include "lloid_device.h"
@@ -56,12 +57,20 @@ __device__ __forceinline__ float ker_value(int k, int off, int ph, int nup, cons
     return (t >= 0 && t <= 2 * nup) ? taps[ph * kUpTaps + t] : 0.0f;
 }
 
-struct UpArgs {
-    const float *prev;       // level j+1 buffer of this wave's rows, row stride kMixS
-    int n_prev, m0;          // m0: buffer index of the window start
-    int off, ph, nup;
-    const float *taps;       // sub-kernels of this stage, [p][kUpTaps]
+// Polyphase position of lane column c of a block at level index i0 (the
+// block's first output): q0 = floor(i0/p), off = floor(i/p) - q0, ph = i mod p.
+// For p <= 16 a block start is a multiple of 16 past the level's window
+// start lo, so off and ph depend on lo + c only and the kernel fragment of
+// a lane is the same for every block of the level; the block's window of
+// the lower level then starts at m0 = (16 / p) cb.
+struct UpPos {
+    int off, ph;
 };
+__device__ __forceinline__ UpPos up_pos(int i0, int c, int logp) {
+    const int q0 = i0 >> logp;   // arithmetic shift: floor for negative indices
+    const int ii = i0 + c;
+    return UpPos{(ii >> logp) - q0, ii & ((1 << logp) - 1)};
+}
 
 // Per slice, a wave addresses W~ and its basis-output ring through buffer
 // resources: per-lane byte offsets (row of W~, ring position of each of its
@@ -114,15 +123,30 @@ struct MixF32 {
             }
         }
     }
-    // 24-wide window, six K-steps of 4
-    static __device__ __forceinline__ void upsample(const UpArgs &u, int li, int lg, floatx4 (&acc)[kRB]) {
+    // level buffer: float [kMixTM][kMixS]
+    static constexpr int LVL_BYTES = kMixTM * kMixS * 4;
+    static __device__ __forceinline__ void lvl_store(void *lvl, int row, int col, float v) {
+        static_cast<float *>(lvl)[row * kMixS + col] = v;
+    }
+    // 24-wide window, six K-steps of 4; lane group g holds Ker[4t + g][c]
+    struct KerF {
+        float b[6];
+    };
+    static __device__ __forceinline__ KerF ker(UpPos u, int nup, const float *taps, int lg) {
+        KerF k;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) k.b[t] = ker_value(4 * t + lg, u.off, u.ph, nup, taps);
+        return k;
+    }
+    static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, int logp,
+                                                    const KerF &k, int li, int lg, floatx4 (&acc)[kRB]) {
+        (void)logp;
+        const float *prev = static_cast<const float *>(lvl) + rw * kMixS;
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
-            const int kk = 4 * t + lg;
-            const float b = ker_value(kk, u.off, u.ph, u.nup, u.taps);
-            const int idx = min(u.m0 + kk, u.n_prev - 1);
+            const int idx = min(m0 + 4 * t + lg, n_prev - 1);
 #pragma unroll
-            for (int m = 0; m < kRB; ++m) acc[m] = mfma_16x16x4_f32(u.prev[(16 * m + li) * kMixS + idx], b, acc[m]);
+            for (int m = 0; m < kRB; ++m) acc[m] = mfma_16x16x4_f32(prev[(16 * m + li) * kMixS + idx], k.b[t], acc[m]);
         }
     }
 };
@@ -184,31 +208,70 @@ struct Mix16 {
             }
         }
     }
+    // level buffer: T hi [kMixTM][SB] then T lo [kMixTM][SB], written once
+    // per level as hi = T(v), lo = T(v - hi).  SB = 152: 304-byte rows keep
+    // 16-byte fragments aligned, and the widest read (a level-1 window of
+    // 145 plus the 8 columns an idle lane group re-reads) fits.
+    static constexpr int SB = 152;
+    static constexpr int LVL_BYTES = 2 * kMixTM * SB * 2;
+    static __device__ __forceinline__ void lvl_store(void *lvl, int row, int col, float v) {
+        T *hi = static_cast<T *>(lvl);
+        const T h = (T)v;
+        hi[row * SB + col] = h;
+        hi[kMixTM * SB + row * SB + col] = (T)(v - (float)h);
+    }
     // 32-wide window, one K-step; both operands split (three products), so
-    // the interpolation keeps ~16 (bf16) or ~22 (fp16) significant bits
-    static __device__ __forceinline__ void upsample(const UpArgs &u, int li, int lg, floatx4 (&acc)[kRB]) {
-        T8 kh, kl;
+    // the interpolation keeps ~16 (bf16) or ~22 (fp16) significant bits.
+    // Ker[k][c] is zero for k >= 24 (off <= 7), so lane group 3 re-reads
+    // group 2's window (finite values) instead of columns past the row.
+    struct KerF {
+        T8 h, l;
+    };
+    static __device__ __forceinline__ KerF ker(UpPos u, int nup, const float *taps, int lg) {
+        KerF k;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-            const float kv = ker_value(8 * lg + j, u.off, u.ph, u.nup, u.taps);
+            const float kv = ker_value(8 * lg + j, u.off, u.ph, nup, taps);
             const T h = (T)kv;
-            kh[j] = h;
-            kl[j] = (T)(kv - (float)h);
+            k.h[j] = h;
+            k.l[j] = (T)(kv - (float)h);
         }
+        return k;
+    }
+    static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, int logp,
+                                                    const KerF &k, int li, int lg, floatx4 (&acc)[kRB]) {
+        (void)n_prev;
+        const T *hi = static_cast<const T *>(lvl);
+        const int e = m0 + 8 * min(lg, 2);
 #pragma unroll
         for (int m = 0; m < kRB; ++m) {
-            T8 ph, pl;
+            const T *ph = hi + (rw + 16 * m + li) * SB + e;
+            const T *pl = ph + kMixTM * SB;
+            T8 ah, al;
+            if (logp == 1) {   // m0 = 8 cb: 16-byte aligned
+                ah = *reinterpret_cast<const T8 *>(ph);
+                al = *reinterpret_cast<const T8 *>(pl);
+            } else if (logp == 2) {   // m0 = 4 cb: 8-byte aligned
+                typedef T T4 __attribute__((ext_vector_type(4)));
+                const T4 h0 = *reinterpret_cast<const T4 *>(ph), h1 = *reinterpret_cast<const T4 *>(ph + 4);
+                const T4 l0 = *reinterpret_cast<const T4 *>(pl), l1 = *reinterpret_cast<const T4 *>(pl + 4);
 #pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int idx = min(u.m0 + 8 * lg + j, u.n_prev - 1);
-                const float pv = u.prev[(16 * m + li) * kMixS + idx];
-                const T h = (T)pv;
-                ph[j] = h;
-                pl[j] = (T)(pv - (float)h);
+                for (int j = 0; j < 4; ++j) {
+                    ah[j] = h0[j];
+                    ah[j + 4] = h1[j];
+                    al[j] = l0[j];
+                    al[j + 4] = l1[j];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    ah[j] = ph[j];
+                    al[j] = pl[j];
+                }
             }
-            acc[m] = mfma16(ph, kl, acc[m]);
-            acc[m] = mfma16(pl, kh, acc[m]);
-            acc[m] = mfma16(ph, kh, acc[m]);
+            acc[m] = mfma16(ah, k.l, acc[m]);
+            acc[m] = mfma16(al, k.h, acc[m]);
+            acc[m] = mfma16(ah, k.h, acc[m]);
         }
     }
 };
@@ -221,7 +284,8 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                                                   PartialPeak *__restrict__ partials, int32_t F, int32_t S,
                                                   int32_t nup, int32_t n_items, int32_t group,
                                                   const int64_t *__restrict__ stride_ctr) {
-    extern __shared__ float lvl[];   // [kMixTM][kMixS]: one level of the chain, then the bank's taps
+    extern __shared__ __attribute__((aligned(16))) char lds[];   // one level of the chain, then the bank's taps
+    void *lvl = lds;
     __shared__ PeakCand wbest[4][8 * kRB];
     const int item = xcd_item(group);
     if (item >= n_items) return;
@@ -236,11 +300,14 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
     const int li = lane & 15, lg = lane >> 4;
     // the polyphase sub-kernels of every stage of the bank, read by the
     // upsampling (first used after the lowest level's barriers)
-    float *tp = lvl + kMixTM * kMixS;
+    float *tp = reinterpret_cast<float *>(lds + Op::LVL_BYTES);
     for (int j = 1; j < B.nlev; ++j) {
         const float *src = uptaps + (B.p[j] - 1) * kUpTaps;
         for (int e = tid; e < B.p[j] * kUpTaps; e += 256) tp[B.up_off[j] + e] = src[e];
     }
+    // the upsampling reads a few columns past a level's window (weighted by
+    // zero taps): the buffer starts as zeros and only ever holds finite values
+    for (int e = tid; e < Op::LVL_BYTES / 16; e += 256) reinterpret_cast<uint4 *>(lds)[e] = uint4{0, 0, 0, 0};
 
     int lo_prev = 0;
     for (int j = B.nlev - 1; j >= 0; --j) {
@@ -285,16 +352,20 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
             const int logp = B.shp[j + 1];
             const float *taps = tp + B.up_off[j + 1];
             const int n_prev = B.n[j + 1];
+            // for p <= 16 one kernel fragment serves every block of the level
+            const typename Op::KerF k0 = Op::ker(up_pos(lo, li, logp), nup, taps, lg);
 #pragma unroll
             for (int i = 0; i < kCB; ++i) {
                 const int cb = wc + kWC * i;
                 if (cb >= nb) continue;   // wave-uniform
                 const int i0 = lo + cb * 16;
-                const int q0 = i0 >> logp;   // arithmetic shift: floor for negative indices
-                const int ii = i0 + li;
-                const UpArgs ua{lvl + rw * kMixS, n_prev, q0 - nup - lo_prev, (ii >> logp) - q0,
-                                ii & ((1 << logp) - 1), nup, taps};
-                Op::upsample(ua, li, lg, acc[i]);
+                const int m0 = (i0 >> logp) - nup - lo_prev;
+                if (logp <= 4) {
+                    Op::upsample(lvl, rw, m0, n_prev, logp, k0, li, lg, acc[i]);
+                } else {
+                    const typename Op::KerF kb = Op::ker(up_pos(i0, li, logp), nup, taps, lg);
+                    Op::upsample(lvl, rw, m0, n_prev, logp, kb, li, lg, acc[i]);
+                }
                 __builtin_amdgcn_sched_barrier(0);   // keep one block's LDS reads in flight at a time
             }
         }
@@ -309,7 +380,7 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
 #pragma unroll
                 for (int m = 0; m < kRB; ++m)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) lvl[(rw + 16 * m + 4 * lg + v) * kMixS + c] = acc[i][m][v];
+                    for (int v = 0; v < 4; ++v) Op::lvl_store(lvl, rw + 16 * m + 4 * lg + v, c, acc[i][m][v]);
             }
             __syncthreads();   // level j complete before it is read as prev
             lo_prev = lo;
@@ -370,8 +441,14 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
 }
 
 size_t mix_lds(int precision, int S, int TP) {
-    if (precision < LLOID_FP32 || precision > LLOID_FP8_BF16 || S != kMixS) return 0;
-    return (size_t)(kMixTM * kMixS + TP) * sizeof(float);
+    if (S != kMixS) return 0;
+    switch (precision) {
+        case LLOID_FP32: return (size_t)MixF32::LVL_BYTES + (size_t)TP * sizeof(float);
+        case LLOID_BF16X3:
+        case LLOID_FP8_BF16: return (size_t)Mix16<__bf16, bf16x8, true>::LVL_BYTES + (size_t)TP * sizeof(float);
+        case LLOID_FP16: return (size_t)Mix16<_Float16, halfx8, false>::LVL_BYTES + (size_t)TP * sizeof(float);
+        default: return 0;
+    }
 }
 
 hipError_t configure_down_lds(size_t down_bytes);
