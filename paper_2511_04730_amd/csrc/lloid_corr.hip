@@ -123,6 +123,7 @@ struct CorrF32 {
         }
     }
     static __device__ __forceinline__ float scale(const CorrItem &, int) { return 1.0f; }
+    using RingT = float;
 };
 
 // ---------------------------------------------------------------- 16-bit
@@ -215,6 +216,7 @@ struct Corr16 {
         }
     }
     static __device__ __forceinline__ float scale(const CorrItem &, int) { return 1.0f; }
+    using RingT = T;
 };
 
 // ------------------------------------------------------------------ FP8
@@ -294,7 +296,35 @@ struct Corr8 {
         }
     }
     static __device__ __forceinline__ float scale(const CorrItem &it, int row) { return it.uscale[it.r0 + row]; }
+    using RingT = __bf16;   // the FP8 form mixes in BF16x3
 };
+
+// Four consecutive basis outputs of one sample into the time-major ring at
+// position pos and its mirror pos + capY: FP32, or hi and lo planes.
+template <typename T>
+__device__ __forceinline__ void ring_store4(void *ring, int64_t pos, int row, int Lpad, int capY, float4 v) {
+    const int64_t o = pos * Lpad + row, om = (pos + capY) * Lpad + row;
+    if constexpr (sizeof(T) == 4) {
+        float *r = static_cast<float *>(ring);
+        *reinterpret_cast<float4 *>(r + o) = v;
+        *reinterpret_cast<float4 *>(r + om) = v;
+    } else {
+        typedef T T4 __attribute__((ext_vector_type(4)));
+        const float x[4] = {v.x, v.y, v.z, v.w};
+        T4 h, l;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            h[i] = (T)x[i];
+            l[i] = (T)(x[i] - (float)h[i]);
+        }
+        T *hi = static_cast<T *>(ring);
+        T *lo = hi + 2LL * capY * Lpad;
+        *reinterpret_cast<T4 *>(hi + o) = h;
+        *reinterpret_cast<T4 *>(hi + om) = h;
+        *reinterpret_cast<T4 *>(lo + o) = l;
+        *reinterpret_cast<T4 *>(lo + om) = l;
+    }
+}
 
 // ------------------------------------------------------------------ kernel
 template <typename Op>
@@ -327,6 +357,7 @@ __global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict
         if (kk + Op::TK < it.klen) Op::gload(g, it, posmod(dbase + kk + Op::TK, it.cap), kk + Op::TK, tid);
         Op::compute(sm, acc, it.mb, ncb, wave, li, lg);
     }
+    const int64_t q0 = kstr * it.f + it.la + it.col0;
 #pragma unroll
     for (int i = 0; i < kCB; ++i) {
         if (i >= ncb) continue;
@@ -335,10 +366,17 @@ __global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict
 #pragma unroll
         for (int m = 0; m < kCorrMB; ++m) {
             if (m >= it.mb) continue;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int r = m * 16 + lg * 4 + v;
-                it.part[(int64_t)(it.r0 + r) * it.f + it.col0 + c] = acc[m][i][v] * Op::scale(it, r);
+            const int r = m * 16 + lg * 4;   // this lane's 4 consecutive rows
+            const float4 v = make_float4(acc[m][i][0] * Op::scale(it, r), acc[m][i][1] * Op::scale(it, r + 1),
+                                         acc[m][i][2] * Op::scale(it, r + 2), acc[m][i][3] * Op::scale(it, r + 3));
+            if (it.yring) {
+                ring_store4<typename Op::RingT>(it.yring, (q0 + c) & (it.capY - 1), it.r0 + r, it.Lpad, it.capY, v);
+            } else {
+                float *p = it.part + (int64_t)(it.r0 + r) * it.f + it.col0 + c;
+                p[0] = v.x;
+                p[it.f] = v.y;
+                p[2 * it.f] = v.z;
+                p[3 * it.f] = v.w;
             }
         }
     }

@@ -51,6 +51,10 @@ struct CorrItem {
     int32_t col0, ncols, k0, klen;
     int32_t mb;              // 16-row blocks of this item (<= kCorrMB)
     int32_t r0;              // first basis row of this item
+    // one tap split: the outputs go straight to the basis-output ring (see
+    // MixSlice; new columns q = k f + la + c) instead of a partial plane
+    void *yring;             // ring of this detector, or nullptr
+    int32_t capY, la;
 };
 
 // Deterministic split-K reduction of 64 new columns x 32 basis rows

@@ -190,9 +190,11 @@ lloid_status upload(lloid_plan *P, T **dst, const std::vector<T> &v, hipStream_t
     return LLOID_OK;
 }
 
-// Correlation work items and their split-K reduction for the current tap
-// split P->ksplit: one item per (slice, detector, tap split, 64-column
-// tile), largest first; the partial planes are (re)allocated to match.
+// Correlation work items and their split-K reduction for the current tiling:
+// one item per (slice, detector, tap split, column tile, 128-row block),
+// largest first.  Slices with one split write the basis-output ring
+// directly; the others get partial planes (reallocated to match) and
+// reduction items.
 lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
     const int ND = P->n_det;
     P->release(P->d_corr);
@@ -207,8 +209,9 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
         const int f = s.rate;
         s.nsplit = (s.Npad + P->ksplit - 1) / P->ksplit;
         P->release(s.part);
+        s.part = nullptr;
         s.part_det = (int64_t)s.nsplit * s.Lpad * f;
-        ST_OK(P->alloc(&s.part, (size_t)ND * s.part_det, false));
+        if (s.nsplit > 1) ST_OK(P->alloc(&s.part, (size_t)ND * s.part_det, false));
         for (int det = 0; det < ND; ++det) {
             for (int sp = 0; sp < s.nsplit; ++sp) {
                 const int k0 = sp * P->ksplit;
@@ -220,7 +223,7 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
                     it.Uhi = s.Uhi;
                     it.Ulo = s.Ulo;
                     it.ring = r.base + det * r.det_stride;
-                    it.part = s.part + det * s.part_det + (int64_t)sp * s.Lpad * f;
+                    it.part = s.part ? s.part + det * s.part_det + (int64_t)sp * s.Lpad * f : nullptr;
                     it.uscale = s.uscale;
                     it.off = (int64_t)s.la - s.delay - (s.N - 1);
                     it.Npad = s.Npad;
@@ -233,9 +236,15 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
                     it.klen = klen;
                     it.mb = std::min(kCorrMB, (s.Lpad - r0) / 16);
                     it.r0 = r0;
+                    if (s.nsplit == 1) {   // no reduction: straight to the ring
+                        it.yring = s.yring + det * s.ydet;
+                        it.capY = s.capY;
+                        it.la = s.la;
+                    }
                     items.push_back(it);
                 }
             }
+            if (s.nsplit == 1) continue;
             for (int c0 = 0; c0 < f; c0 += 64)
                 for (int l0 = 0; l0 < s.Lpad; l0 += 32)
                     red.push_back(ReduceItem{s.part + det * s.part_det, s.yring + det * s.ydet, s.nsplit, s.L,
