@@ -66,7 +66,7 @@ typedef enum {
 } lloid_precision;
 
 /* One time slice of one bank (Sec. II.C.1).
- *   rate_hz  f^s, the top rate divided by a power of two (1 allowed)
+ *   rate_hz  f^s, the top rate divided by a power of two D, 1 <= D <= 64
  *   delay    t^s * f^s: time before merger of the slice's latest tap, in
  *            samples at f^s
  *   n_taps   N^s; n_basis L^s with 1 <= L^s <= 160 (and at most 160 basis
@@ -120,8 +120,13 @@ typedef struct lloid_plan lloid_plan;
  * per-detector history buffers.  The plan starts at stride 0 with zero
  * history.  `stream` (hipStream_t or NULL) orders the set-up work; the call
  * synchronises it before returning.
- * Errors: LLOID_E_ARG, LLOID_E_SHAPE, LLOID_E_LATENCY (a slice needs strain
- * from the future of the stride), LLOID_E_NOMEM, LLOID_E_HIP. */
+ * Errors: LLOID_E_ARG, LLOID_E_SHAPE (a rate that is not the top rate over
+ * a power of two, a top rate that is not a multiple of 256, a negative
+ * delay, no taps or basis vectors), LLOID_E_LATENCY (a slice needs strain
+ * from the future of the stride), LLOID_E_UNSUPPORTED (a decimation factor
+ * above 64, more than 160 basis vectors per bank and rate, more than 12
+ * rates per bank, or upsampling taps beyond the mixing kernel's LDS),
+ * LLOID_E_NOMEM, LLOID_E_HIP. */
 lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *banks,
                                int32_t n_banks, void *stream, lloid_plan **out);
 

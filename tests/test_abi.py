@@ -85,6 +85,10 @@ def test_shape_errors(L):
     assert _create(L, [bad]) == -2                      # rate not top / power of two
     big = synth.Bank(4, [synth.Slice(1024, 0, np.zeros((161, 200)), np.zeros((8, 161)))])
     assert _create(L, [big]) == -7                      # more than 160 basis vectors
+    deep = synth.Bank(4, [synth.Slice(8, 100, np.zeros((4, 64)), np.zeros((8, 4)))])
+    assert _create(L, [deep]) == -7                     # decimation 128 > 64
+    neg = synth.Bank(4, [synth.Slice(1024, -1, bank.slices[0].basis, bank.slices[0].mixing)])
+    assert _create(L, [neg]) == -2                      # negative delay
 
 
 def test_latency_error_matches_oracle(L):
