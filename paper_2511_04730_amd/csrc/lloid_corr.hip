@@ -299,11 +299,12 @@ struct Corr8 {
     using RingT = __bf16;   // the FP8 form mixes in BF16x3
 };
 
-// Four consecutive basis outputs of one sample into the time-major ring at
+// Four consecutive basis outputs row .. row + 3 (row a multiple of 4, so
+// inside one 16-byte group) of one sample into the basis-output ring at
 // position pos and its mirror pos + capY: FP32, or hi and lo planes.
 template <typename T>
 __device__ __forceinline__ void ring_store4(void *ring, int64_t pos, int row, int Lpad, int capY, float4 v) {
-    const int64_t o = pos * Lpad + row, om = (pos + capY) * Lpad + row;
+    const int64_t o = ring_index<16 / sizeof(T)>(pos, row, capY), om = ring_index<16 / sizeof(T)>(pos + capY, row, capY);
     if constexpr (sizeof(T) == 4) {
         float *r = static_cast<float *>(ring);
         *reinterpret_cast<float4 *>(r + o) = v;

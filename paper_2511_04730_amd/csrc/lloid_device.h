@@ -35,6 +35,17 @@ __device__ __forceinline__ V buffer_load16(__amdgpu_buffer_rsrc_t r, int voff, i
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+// Element (pos, l) of one plane of a basis-output ring and element (r, l) of
+// a mixing matrix in fragment order (layouts in MixSlice); G = 16 / element size.
+template <int G>
+__device__ __forceinline__ int64_t ring_index(int64_t pos, int l, int capY) {
+    return ((int64_t)(l / G) * 2 * capY + pos) * G + l % G;
+}
+template <int G>
+__device__ __forceinline__ int64_t frag_index(int r, int l, int Lpad) {
+    return ((int64_t)(r >> 4) * (Lpad / G) + l / G) * (16 * G) + (r & 15) * G + l % G;
+}
+
 // Work item of this work group when `group` consecutive items are to share
 // one XCD (and its L2): the dispatcher deals work groups to the XCDs in turn,
 // so group b runs on XCD b mod kXcds.  group <= 0 keeps the launch order.

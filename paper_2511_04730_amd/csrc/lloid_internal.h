@@ -59,7 +59,7 @@ struct CorrItem {
 
 // Deterministic split-K reduction of 64 new columns x 32 basis rows
 // [l0, l0 + 32) of one slice and detector into its basis-output ring
-// (time-major, see MixSlice).
+// (see MixSlice for the layout).
 struct ReduceItem {
     const float *part;       // [nsplit][Lpad][f]
     void *yring;             // ring of this detector
@@ -76,14 +76,23 @@ struct DownItem {
 };
 
 // Mixing + upsample-and-add (Sec. II.C.2 "Upsampling", "Combining", Sec. II.C.3).
-// Basis-output ring of a slice and detector: time-major mirror ring of
-// 2 capY rows (capY a power of two; position q at q mod capY and
-// q mod capY + capY), each row the Lpad basis outputs of one sample:
-//   FP32 form:   float [2 capY][Lpad]
-//   16-bit forms: T hi [2 capY][Lpad], then T lo [2 capY][Lpad]  (y = hi + lo)
+// Basis-output ring of a slice and detector: a mirror ring of 2 capY
+// positions (capY a power of two; position q at q mod capY and
+// q mod capY + capY) holding the Lpad basis outputs of each sample, in
+// 16-byte groups of G = 16 / sizeof(T) consecutive outputs: group g of every
+// position comes before group g + 1, i.e. element (pos, l) of a plane is at
+//   ((l / G) 2 capY + pos) G + l mod G
+// so the 16-byte MFMA fragments of 16 consecutive positions are 256
+// contiguous bytes.
+//   FP32 form:    one float plane (G = 4)
+//   16-bit forms: T hi plane, then T lo plane, y = hi + lo (G = 8)
 // Either way 4 bytes per element; ydet counts 4-byte elements.
+// The mixing rows are stored in fragment order: 16 x G tiles of the
+// [rows_pad][Lpad] matrix, tile (r / 16, l / G) at ((r / 16) (Lpad / G) +
+// l / G) 16 G, row-major inside, so that one K group of a 16-row fragment
+// is 256 contiguous bytes.
 struct MixSlice {
-    const float *W;          // [rows_pad][Lpad] fp32 normalised mixing rows
+    const float *W;          // fp32 normalised mixing rows (fragment order)
     const void *Whi;         // reduced precision
     const void *Wlo;
     const void *Y;           // basis-output ring of detector 0
@@ -153,7 +162,7 @@ inline size_t mix_lds_bytes(int precision, int S, int TP) { return mix_lds(preci
 hipError_t launch_convert_fp8_rows(hipStream_t, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
                                    uint8_t *dst, int32_t dst_ld, float *scale);
 
-// rows [0, rows) of a time-major basis-output ring, positions a .. a+len-1,
+// rows [0, rows) of a basis-output ring, positions a .. a+len-1,
 // as float rows dst[r * dst_ld + dst_off + c]
 hipError_t launch_ring_gather(hipStream_t, int precision, const void *ring, int32_t Lpad, int32_t cap, int64_t a,
                               int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off);
@@ -182,7 +191,8 @@ hipError_t launch_convert_rows(hipStream_t, const double *src, int32_t rows, int
                                float *dst32, void *dst_hi, void *dst_lo, int32_t dst_ld,
                                float *row_scale_out);
 
-// roles for launch_convert_rows
-enum { ROLE_BASIS = 0, ROLE_MIXING = 1 };
+// destination layouts of launch_convert_rows: row-major [rows][dst_ld], or
+// the mixing kernel's fragment order (see MixSlice)
+enum { ROLE_ROWS = 0, ROLE_MIXING = 1 };
 
 }  // namespace lloid

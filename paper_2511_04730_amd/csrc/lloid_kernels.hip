@@ -91,8 +91,9 @@ hipError_t launch_down(const LaunchCtx &ctx, const DownItem *items, int32_t n_it
 
 // Sum the split partials of 64 new columns x 32 basis rows in a fixed
 // order (split 0 first), transpose through LDS and append them to the
-// time-major ring: one row of Lpad outputs per sample, rows L .. Lpad-1
-// zero.  16-bit forms store y as hi = T(y) and lo = T(y - hi) in two planes.
+// basis-output ring (16-byte groups of consecutive outputs per sample,
+// outputs L .. Lpad-1 zero).  16-bit forms store y as hi = T(y) and
+// lo = T(y - hi) in two planes.
 template <typename T>
 __global__ __launch_bounds__(256) void reduce_kernel(const ReduceItem *__restrict__ items,
                                                      const int64_t *__restrict__ stride_ctr) {
@@ -116,11 +117,12 @@ __global__ __launch_bounds__(256) void reduce_kernel(const ReduceItem *__restric
     constexpr int V = sizeof(T) == 4 ? 4 : 8;   // outputs per thread and row: 16 bytes
     const int nrow = min(32, it.Lpad - it.l0);
     const int groups = nrow / V;
+    // consecutive threads write consecutive positions of one 16-byte group
     for (int e = threadIdx.x; e < ncols * groups; e += 256) {
-        const int c = e / groups, l = (e % groups) * V;
+        const int c = e % ncols, l = (e / ncols) * V;
         const int64_t pos = (q0 + c) & mask;
-        const int64_t o = pos * it.Lpad + it.l0 + l;
-        const int64_t om = (pos + it.capY) * it.Lpad + it.l0 + l;
+        const int64_t o = ring_index<V>(pos, it.l0 + l, it.capY);
+        const int64_t om = ring_index<V>(pos + it.capY, it.l0 + l, it.capY);
         if constexpr (sizeof(T) == 4) {
             const float4 v = make_float4(sm[l][c], sm[l + 1][c], sm[l + 2][c], sm[l + 3][c]);
             float *ring = static_cast<float *>(it.yring);
@@ -174,11 +176,12 @@ __global__ void ring_gather_kernel(const void *__restrict__ ring, int32_t Lpad, 
     if (r >= rows || c >= len) return;
     const int64_t p = posmod(a, cap) + c;   // mirror ring: p < 2 cap
     float v;
+    const int64_t o = ring_index<16 / sizeof(T)>(p, r, cap);
     if constexpr (sizeof(T) == 4) {
-        v = static_cast<const float *>(ring)[p * Lpad + r];
+        v = static_cast<const float *>(ring)[o];
     } else {
         const T *hi = static_cast<const T *>(ring);
-        v = (float)hi[p * Lpad + r] + (float)hi[2LL * cap * Lpad + p * Lpad + r];
+        v = (float)hi[o] + (float)hi[2LL * cap * Lpad + o];
     }
     dst[r * dst_ld + dst_off + c] = v;
 }
@@ -264,32 +267,36 @@ hipError_t launch_normalize(hipStream_t st, const double *const *W64, const int3
 
 // v = src * row_scale -> hi = T(v) (round to nearest even), lo = T(v - hi)
 // with the residual formed in FP64 (lo is skipped when dst_lo is NULL).
+// The destination is row-major [rows][dst_ld] or, for frag != 0, the mixing
+// kernel's fragment order over a [rows_pad][dst_ld] matrix (the caller's
+// buffer holds the padding, zero-filled).
 template <typename T>
 __global__ void convert_split_kernel(const double *__restrict__ src, int32_t rows, int32_t cols, int32_t src_ld,
                                      const double *__restrict__ row_scale, T *__restrict__ hi, T *__restrict__ lo,
-                                     int32_t dst_ld) {
+                                     int32_t dst_ld, int32_t frag) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)rows * cols) return;
     const int r = (int)(e / cols), c = (int)(e % cols);
     const double v = src[(int64_t)r * src_ld + c] * (row_scale ? row_scale[r] : 1.0);
+    const int64_t o = frag ? frag_index<8>(r, c, dst_ld) : (int64_t)r * dst_ld + c;
     const T h = (T)(float)v;
-    hi[(int64_t)r * dst_ld + c] = h;
-    if (lo) lo[(int64_t)r * dst_ld + c] = (T)(float)(v - (double)(float)h);
+    hi[o] = h;
+    if (lo) lo[o] = (T)(float)(v - (double)(float)h);
 }
 
 hipError_t launch_convert_reduced(hipStream_t st, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
                                   const double *row_scale, int precision, int role, void *dst_hi, void *dst_lo,
                                   int32_t dst_ld, float *row_scale_out) {
-    (void)role;
     (void)row_scale_out;
+    const int32_t frag = role == ROLE_MIXING;
     const int64_t n = (int64_t)rows * cols;
     const dim3 grid((unsigned)((n + 255) / 256));
     if (precision == LLOID_BF16X3 || precision == LLOID_FP8_BF16) {
         hipLaunchKernelGGL(convert_split_kernel<__bf16>, grid, dim3(256), 0, st, src, rows, cols, src_ld, row_scale,
-                           static_cast<__bf16 *>(dst_hi), static_cast<__bf16 *>(dst_lo), dst_ld);
+                           static_cast<__bf16 *>(dst_hi), static_cast<__bf16 *>(dst_lo), dst_ld, frag);
     } else if (precision == LLOID_FP16) {
         hipLaunchKernelGGL(convert_split_kernel<_Float16>, grid, dim3(256), 0, st, src, rows, cols, src_ld,
-                           row_scale, static_cast<_Float16 *>(dst_hi), static_cast<_Float16 *>(dst_lo), dst_ld);
+                           row_scale, static_cast<_Float16 *>(dst_hi), static_cast<_Float16 *>(dst_lo), dst_ld, frag);
     } else {
         return hipErrorNotSupported;
     }
@@ -297,12 +304,13 @@ hipError_t launch_convert_reduced(hipStream_t st, const double *src, int32_t row
 }
 
 __global__ void convert_f32_kernel(const double *__restrict__ src, int32_t rows, int32_t cols, int32_t src_ld,
-                                   const double *__restrict__ row_scale, float *__restrict__ dst, int32_t dst_ld) {
+                                   const double *__restrict__ row_scale, float *__restrict__ dst, int32_t dst_ld,
+                                   int32_t frag) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= (int64_t)rows * cols) return;
     const int r = (int)(e / cols), c = (int)(e % cols);
     const double v = src[(int64_t)r * src_ld + c] * (row_scale ? row_scale[r] : 1.0);
-    dst[(int64_t)r * dst_ld + c] = (float)v;
+    dst[frag ? frag_index<4>(r, c, dst_ld) : (int64_t)r * dst_ld + c] = (float)v;
 }
 
 hipError_t launch_convert_rows(hipStream_t st, const double *src, int32_t rows, int32_t cols, int32_t src_ld,
@@ -312,7 +320,7 @@ hipError_t launch_convert_rows(hipStream_t st, const double *src, int32_t rows, 
     if (n == 0) return hipSuccess;
     if (dst32) {
         hipLaunchKernelGGL(convert_f32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, rows,
-                           cols, src_ld, row_scale, dst32, dst_ld);
+                           cols, src_ld, row_scale, dst32, dst_ld, (int32_t)(role == ROLE_MIXING));
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

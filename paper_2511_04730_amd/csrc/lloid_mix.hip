@@ -3,7 +3,7 @@
 // "Filtering and reconstruction", "Upsampling SNR segments", "Combining SNR
 // segments"; the recursion of the pre-synchronisation equation, Sec. II.C.3).
 //
-// One work group = kMixTM = 64 real rows (32 templates) x kMixTN = 256
+// One work group = kMixTM = 128 real rows (64 templates) x kMixTN = 256
 // top-rate samples of one bank and detector.  Levels run lowest rate first;
 // level j covers the local window [lo_j + t0/P_j, +n_j): the tile plus the
 // halo its upper level reads.  Per level:
@@ -13,13 +13,14 @@
 // series (interleaved re, im) and to the running trigger candidates.
 //
 // Both operands of the mixing contraction come straight from memory into
-// MFMA registers (buffer loads, double-buffered over basis-row steps), with
-// no LDS staging and no barrier: W~ rows are row-major
-// [rows][Lpad] and the basis-output rings are time-major [position][Lpad]
-// (one row per sample), so the K elements a lane supplies (8 consecutive
-// basis rows for the 16-bit forms, 4 for FP32) are one 16-byte load on
-// either side.  The 16-bit rings already hold y as hi + lo, split once when
-// the reduction appends them.  Each wave owns the column blocks
+// MFMA registers (buffer loads), with no LDS staging and no barrier.  The
+// K elements a lane supplies (8 consecutive basis rows for the 16-bit
+// forms, 4 for FP32) are one 16-byte load on either side, and both operands
+// are stored so that the 16 lanes of a K group read 256 contiguous bytes:
+// W~ in 16-row fragment order, the basis-output rings grouped by 16 bytes
+// of outputs with consecutive positions adjacent (layouts in MixSlice).
+// The 16-bit rings already hold y as hi + lo, split once when they are
+// written.  Each wave owns the column blocks
 // cb = wave, wave + 4, ... of the window and all four 16-row blocks, so
 // every y fragment it loads feeds four row blocks.
 //
@@ -84,6 +85,7 @@ struct MixF32 {
     static constexpr int K = 16;
     struct Src {
         __amdgpu_buffer_rsrc_t w, y;
+        int ys;                  // ring bytes per basis row step
         int va[kRB], vb[kCB];
     };
     struct FragA {
@@ -94,20 +96,22 @@ struct MixF32 {
     };
     static __device__ __forceinline__ void init(Src &s, const MixSlice &ms, const void *ring, int r0, const int (&p)[kCB],
                                                 int li, int lg) {
-        s.w = buffer_rsrc(ms.W, (uint32_t)ms.rows_pad * ms.Lpad * 4);   // r0: first row of this wave
+        // r0: first row of this wave (a multiple of 16)
+        s.w = buffer_rsrc(ms.W, (uint32_t)ms.rows_pad * ms.Lpad * 4);
         s.y = buffer_rsrc(ring, (uint32_t)(2 * ms.capY) * ms.Lpad * 4);
+        s.ys = 8 * ms.capY;
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) s.va[m] = ((r0 + 16 * m + li) * ms.Lpad + 4 * lg) * 4;
+        for (int m = 0; m < kRB; ++m) s.va[m] = (((r0 >> 4) + m) * (ms.Lpad / 4) + lg) * 256 + 16 * li;
 #pragma unroll
-        for (int i = 0; i < kCB; ++i) s.vb[i] = (p[i] * ms.Lpad + 4 * lg) * 4;
+        for (int i = 0; i < kCB; ++i) s.vb[i] = (lg * 2 * ms.capY + p[i]) * 16;
     }
     static __device__ __forceinline__ void load_a(FragA &f, const Src &s, int l0) {
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) f.a[m] = buffer_load16<float4>(s.w, s.va[m], l0 * 4);
+        for (int m = 0; m < kRB; ++m) f.a[m] = buffer_load16<float4>(s.w, s.va[m], l0 * 64);
     }
     static __device__ __forceinline__ void load_b(FragB &f, const Src &s, int l0, int i0) {
 #pragma unroll
-        for (int i = 0; i < kCBH; ++i) f.b[i] = buffer_load16<float4>(s.y, s.vb[i0 + i], l0 * 4);
+        for (int i = 0; i < kCBH; ++i) f.b[i] = buffer_load16<float4>(s.y, s.vb[i0 + i], l0 * s.ys);
     }
     static __device__ __forceinline__ void mma(floatx4 (&acc)[kCB][kRB], const FragA &a, const FragB &f, int i0,
                                                int ncb) {
@@ -161,6 +165,7 @@ struct Mix16 {
     struct Src {
         __amdgpu_buffer_rsrc_t wh, wl, y;
         int ylo;                 // byte offset of the ring's lo plane
+        int ys;                  // ring bytes per basis row step
         int va[kRB], vb[kCB];
     };
     struct FragA {
@@ -176,23 +181,24 @@ struct Mix16 {
         if constexpr (SPLIT_W) s.wl = buffer_rsrc(ms.Wlo, wbytes);
         s.ylo = 2 * ms.capY * ms.Lpad * 2;
         s.y = buffer_rsrc(ring, 2u * s.ylo);
+        s.ys = 4 * ms.capY;
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) s.va[m] = ((r0 + 16 * m + li) * ms.Lpad + 8 * lg) * 2;
+        for (int m = 0; m < kRB; ++m) s.va[m] = (((r0 >> 4) + m) * (ms.Lpad / 8) + lg) * 256 + 16 * li;
 #pragma unroll
-        for (int i = 0; i < kCB; ++i) s.vb[i] = (p[i] * ms.Lpad + 8 * lg) * 2;
+        for (int i = 0; i < kCB; ++i) s.vb[i] = (lg * 2 * ms.capY + p[i]) * 16;
     }
     static __device__ __forceinline__ void load_a(FragA &f, const Src &s, int l0) {
 #pragma unroll
         for (int m = 0; m < kRB; ++m) {
-            f.h[m] = buffer_load16<T8>(s.wh, s.va[m], l0 * 2);
-            if constexpr (SPLIT_W) f.l[m] = buffer_load16<T8>(s.wl, s.va[m], l0 * 2);
+            f.h[m] = buffer_load16<T8>(s.wh, s.va[m], l0 * 32);
+            if constexpr (SPLIT_W) f.l[m] = buffer_load16<T8>(s.wl, s.va[m], l0 * 32);
         }
     }
     static __device__ __forceinline__ void load_b(FragB &f, const Src &s, int l0, int i0) {
 #pragma unroll
         for (int i = 0; i < kCBH; ++i) {
-            f.h[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * 2);
-            f.l[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * 2 + s.ylo);
+            f.h[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * s.ys);
+            f.l[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * s.ys + s.ylo);
         }
     }
     static __device__ __forceinline__ void mma(floatx4 (&acc)[kCB][kRB], const FragA &a, const FragB &f, int i0,

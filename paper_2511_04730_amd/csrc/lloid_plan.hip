@@ -29,7 +29,7 @@ using namespace lloid;
 
 namespace {
 
-constexpr uint64_t kStateMagic = 0x4c4c4f4944535432ull;   // "LLOIDST2": time-major basis-output rings
+constexpr uint64_t kStateMagic = 0x4c4c4f4944535433ull;   // "LLOIDST3": grouped basis-output rings
 
 int ilog2(int v) {
     int r = 0;
@@ -62,10 +62,11 @@ struct PSlice {
     int bank, rate, D, level, N, L, Npad, Lpad, la, nsplit, capY;
     int64_t delay;
     float *U32 = nullptr;
-    float *W32 = nullptr;
+    float *W32 = nullptr;    // FP32 mixing rows, row-major (gradient)
+    float *Wf32 = nullptr;   // the same in the mixing kernel's fragment order
     void *Uhi = nullptr, *Ulo = nullptr, *Whi = nullptr, *Wlo = nullptr;
     float *uscale = nullptr;
-    float *yring = nullptr;  // n_det rings of [Lpad][2 capY]
+    float *yring = nullptr;  // n_det rings of Lpad x 2 capY (layout in MixSlice)
     int64_t ydet = 0;
     float *part = nullptr;   // n_det x [nsplit][Lpad][f]
     int64_t part_det = 0;
@@ -475,10 +476,13 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                                       st));
                 if (P->precision == LLOID_FP32) {
                     ST_OK(P->alloc(&ps.W32, (size_t)pb.rows_pad * ps.Lpad));
-                    HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, LLOID_FP32, ROLE_MIXING, ps.W32,
+                    ST_OK(P->alloc(&ps.Wf32, (size_t)pb.rows_pad * ps.Lpad));
+                    HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, LLOID_FP32, ROLE_ROWS, ps.W32,
+                                               nullptr, nullptr, ps.Lpad, nullptr));
+                    HIP_OK(launch_convert_rows(st, w64[id], rows, ps.L, ps.L, inv, LLOID_FP32, ROLE_MIXING, ps.Wf32,
                                                nullptr, nullptr, ps.Lpad, nullptr));
                     ST_OK(P->alloc(&ps.U32, (size_t)ps.Lpad * ps.Npad));
-                    HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, LLOID_FP32, ROLE_BASIS, ps.U32,
+                    HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, LLOID_FP32, ROLE_ROWS, ps.U32,
                                                nullptr, nullptr, ps.Npad, nullptr));
                 } else {
                     // 16-bit parts: hi and lo of W (bf16x3) or W alone (fp16);
@@ -499,7 +503,7 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                     } else {
                         ST_OK(P->alloc(&uh, (size_t)ps.Lpad * ps.Npad));
                         if (P->precision == LLOID_BF16X3) ST_OK(P->alloc(&ul, (size_t)ps.Lpad * ps.Npad));
-                        HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, P->precision, ROLE_BASIS,
+                        HIP_OK(launch_convert_rows(st, u64, ps.L, ps.N, ps.N, nullptr, P->precision, ROLE_ROWS,
                                                    nullptr, uh, ul, ps.Npad, nullptr));
                     }
                     ps.Whi = wh;
@@ -620,7 +624,7 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
                     PSlice &s = P->slices[id];
                     if (s.level != j) continue;
                     if (m.n[j] > s.capY) return LLOID_E_UNSUPPORTED;   // a tile's window must fit the ring
-                    ms.push_back(MixSlice{s.W32, s.Whi, s.Wlo, s.yring, s.ydet, s.L, s.Lpad, s.capY, s.level, pb.rows_pad, 0});
+                    ms.push_back(MixSlice{s.Wf32, s.Whi, s.Wlo, s.yring, s.ydet, s.L, s.Lpad, s.capY, s.level, pb.rows_pad, 0});
                 }
             }
             m.slice_begin[pb.nlev] = (int)ms.size();
@@ -1212,15 +1216,22 @@ lloid_status lloid_set_slice(lloid_plan *P, int32_t slice, const double *U, cons
     PSlice &s = P->slices[slice];
     const int rows = 2 * P->banks[s.bank].M;
     if (P->precision == LLOID_FP32) {
-        HIP_OK(launch_convert_rows(st, W, rows, s.L, s.L, nullptr, LLOID_FP32, ROLE_MIXING, s.W32, nullptr, nullptr,
+        HIP_OK(launch_convert_rows(st, W, rows, s.L, s.L, nullptr, LLOID_FP32, ROLE_ROWS, s.W32, nullptr, nullptr,
                                    s.Lpad, nullptr));
-        HIP_OK(launch_convert_rows(st, U, s.L, s.N, s.N, nullptr, LLOID_FP32, ROLE_BASIS, s.U32, nullptr, nullptr,
+        HIP_OK(launch_convert_rows(st, W, rows, s.L, s.L, nullptr, LLOID_FP32, ROLE_MIXING, s.Wf32, nullptr, nullptr,
+                                   s.Lpad, nullptr));
+        HIP_OK(launch_convert_rows(st, U, s.L, s.N, s.N, nullptr, LLOID_FP32, ROLE_ROWS, s.U32, nullptr, nullptr,
                                    s.Npad, nullptr));
     } else {
         HIP_OK(launch_convert_rows(st, W, rows, s.L, s.L, nullptr, P->precision, ROLE_MIXING, nullptr, s.Whi, s.Wlo,
                                    s.Lpad, nullptr));
-        HIP_OK(launch_convert_rows(st, U, s.L, s.N, s.N, nullptr, P->precision, ROLE_BASIS, nullptr, s.Uhi, s.Ulo,
-                                   s.Npad, nullptr));
+        if (P->precision == LLOID_FP8_BF16) {
+            // e4m3 basis with its per-vector scales, as at plan creation
+            HIP_OK(launch_convert_fp8_rows(st, U, s.L, s.N, s.N, static_cast<uint8_t *>(s.Uhi), s.Npad, s.uscale));
+        } else {
+            HIP_OK(launch_convert_rows(st, U, s.L, s.N, s.N, nullptr, P->precision, ROLE_ROWS, nullptr, s.Uhi, s.Ulo,
+                                       s.Npad, nullptr));
+        }
     }
     HIP_OK(hipStreamSynchronize(st));
     return LLOID_OK;
