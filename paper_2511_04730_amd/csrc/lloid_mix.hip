@@ -7,20 +7,26 @@
 // top-rate samples of one bank and detector.  Levels run lowest rate first;
 // level j covers the local window [lo_j + t0/P_j, +n_j): the tile plus the
 // halo its upper level reads.  Per level:
-//   acc = sum over slices at rate j of W~^s (rows) x y^s (window)   [MFMA]
-//       + H_up(level j+1)                                           [MFMA]
+//   acc = H_up(level j+1)                                           [MFMA]
+//       + sum over slices at rate j of W~^s (rows) x y^s (window)   [MFMA]
 // Level j >= 1 is kept in LDS for the next level; level 0 goes to the SNR
 // series (interleaved re, im) and to the running trigger candidates.
 //
-// Both operands of the mixing contraction come straight from memory into
-// MFMA registers (buffer loads), with no LDS staging and no barrier.  The
-// K elements a lane supplies (8 consecutive basis rows for the 16-bit
-// forms, 4 for FP32) are one 16-byte load on either side, and both operands
-// are stored so that the 16 lanes of a K group read 256 contiguous bytes:
-// W~ in 16-row fragment order, the basis-output rings grouped by 16 bytes
-// of outputs with consecutive positions adjacent (layouts in MixSlice).
-// The 16-bit rings already hold y as hi + lo, split once when they are
-// written.  Each wave owns the column blocks
+// The contraction runs over chunks of K basis rows (32 for the 16-bit
+// forms, 16 for FP32).  In the 16-bit forms the work group copies, per
+// chunk, the y window of all its columns from the ring into an LDS stage
+// with asynchronous buffer-to-LDS loads (two stages, in the level buffer,
+// which is free while a level contracts), and every wave loads its W~
+// fragments into registers, both one chunk ahead of the MFMAs.  The FP32
+// form, whose four MFMAs per loaded K group already cover the loads, takes
+// both operands straight from memory into registers.  The K elements a lane
+// supplies (8 consecutive basis rows for the 16-bit forms, 4 for FP32) are
+// one 16-byte access on either side, and both operands are stored so that
+// the 16 lanes of a K group read 256 contiguous bytes: W~ in 16-row
+// fragment order, the basis-output rings (and the stages) grouped by 16
+// bytes of outputs with consecutive positions adjacent (layouts in
+// MixSlice).  The 16-bit rings already hold y as hi + lo, split once when
+// they are written.  Each wave owns the column blocks
 // cb = wave, wave + 4, ... of the window and all four 16-row blocks, so
 // every y fragment it loads feeds four row blocks.
 //
@@ -34,8 +40,9 @@
 // Eq. (upsample)).  off <= 7 and 2 N_up <= 16, so a 24- (FP32) or 32-wide
 // (16-bit) window of prev holds every tap.  One LDS buffer holds a level
 // (FP32, or hi and lo planes split once when the level is written, so that
-// the 16-bit fragments are aligned vector reads); level j's accumulators
-// stay in registers until every wave has read level j+1, then overwrite it.
+// the 16-bit fragments are aligned vector reads).  A level first adds the
+// upsampled level j+1 into its accumulators, then (after a barrier) uses
+// the buffer for its y stages, and finally overwrites it with level j.
 #include <hip/hip_runtime.h>
 
 #include "lloid_device.h"
@@ -50,7 +57,7 @@ namespace lloid {
 constexpr int kWR = 2, kWC = 2;
 constexpr int kRB = kMixTM / (16 * kWR);
 constexpr int kCB = kMixTN / (16 * kWC);
-constexpr int kCBH = kCB / 2;      // column blocks per operand load
+constexpr int kCBH = kCB / 2;      // column blocks per operand load (direct-load form)
 
 __device__ __forceinline__ float ker_value(int k, int off, int ph, int nup, const float *__restrict__ taps) {
     if (ph == 0) return k == off + nup ? 1.0f : 0.0f;
@@ -83,6 +90,9 @@ __device__ __forceinline__ UpPos up_pos(int i0, int c, int logp) {
 // rows l0 + 4g .. l0 + 4g + 3, one per MFMA, on both sides.
 struct MixF32 {
     static constexpr int K = 16;
+    // FP32: the four MFMAs per loaded K group already cover the operand
+    // loads; the direct-load contraction is faster than staging here
+    static constexpr bool STAGED = false;
     struct Src {
         __amdgpu_buffer_rsrc_t w, y;
         int ys;                  // ring bytes per basis row step
@@ -162,56 +172,45 @@ struct MixF32 {
 template <typename T, typename T8, bool SPLIT_W>
 struct Mix16 {
     static constexpr int K = 32;
-    struct Src {
-        __amdgpu_buffer_rsrc_t wh, wl, y;
-        int ylo;                 // byte offset of the ring's lo plane
-        int ys;                  // ring bytes per basis row step
-        int va[kRB], vb[kCB];
+    static constexpr bool STAGED = true;   // y through LDS stages, W~ one chunk ahead
+    static constexpr int PLANES = 2;       // ring planes: hi, lo
+    static constexpr int RING_G = 8;       // ring outputs per 16-byte group
+    struct ASrc {
+        __amdgpu_buffer_rsrc_t wh, wl;
+        int va[kRB];
     };
     struct FragA {
         T8 h[kRB], l[SPLIT_W ? kRB : 1];
     };
     struct FragB {
-        T8 h[kCBH], l[kCBH];
+        T8 h, l;
     };
-    static __device__ __forceinline__ void init(Src &s, const MixSlice &ms, const void *ring, int r0, const int (&p)[kCB],
-                                                int li, int lg) {
+    static __device__ __forceinline__ void init_a(ASrc &s, const MixSlice &ms, int r0, int li, int lg) {
         const uint32_t wbytes = (uint32_t)ms.rows_pad * ms.Lpad * 2;
         s.wh = buffer_rsrc(ms.Whi, wbytes);
         if constexpr (SPLIT_W) s.wl = buffer_rsrc(ms.Wlo, wbytes);
-        s.ylo = 2 * ms.capY * ms.Lpad * 2;
-        s.y = buffer_rsrc(ring, 2u * s.ylo);
-        s.ys = 4 * ms.capY;
 #pragma unroll
         for (int m = 0; m < kRB; ++m) s.va[m] = (((r0 >> 4) + m) * (ms.Lpad / 8) + lg) * 256 + 16 * li;
-#pragma unroll
-        for (int i = 0; i < kCB; ++i) s.vb[i] = (lg * 2 * ms.capY + p[i]) * 16;
     }
-    static __device__ __forceinline__ void load_a(FragA &f, const Src &s, int l0) {
+    static __device__ __forceinline__ void load_a(FragA &f, const ASrc &s, int l0) {
 #pragma unroll
         for (int m = 0; m < kRB; ++m) {
             f.h[m] = buffer_load16<T8>(s.wh, s.va[m], l0 * 32);
             if constexpr (SPLIT_W) f.l[m] = buffer_load16<T8>(s.wl, s.va[m], l0 * 32);
         }
     }
-    static __device__ __forceinline__ void load_b(FragB &f, const Src &s, int l0, int i0) {
-#pragma unroll
-        for (int i = 0; i < kCBH; ++i) {
-            f.h[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * s.ys);
-            f.l[i] = buffer_load16<T8>(s.y, s.vb[i0 + i], l0 * s.ys + s.ylo);
-        }
+    // column block cb of an LDS stage [PLANES][4 groups][ncs][16 bytes]
+    static __device__ __forceinline__ void read_b(FragB &f, const char *stage, int ncs, int cb, int li, int lg) {
+        const char *p = stage + (lg * ncs + cb * 16 + li) * 16;
+        f.h = *reinterpret_cast<const T8 *>(p);
+        f.l = *reinterpret_cast<const T8 *>(p + 4 * ncs * 16);
     }
-    static __device__ __forceinline__ void mma(floatx4 (&acc)[kCB][kRB], const FragA &a, const FragB &f, int i0,
-                                               int ncb) {
+    static __device__ __forceinline__ void mma(floatx4 (&acc)[kRB], const FragA &a, const FragB &f) {
 #pragma unroll
-        for (int i = 0; i < kCBH; ++i) {
-            if (i0 + i >= ncb) continue;
-#pragma unroll
-            for (int m = 0; m < kRB; ++m) {
-                acc[i0 + i][m] = mfma16(a.h[m], f.l[i], acc[i0 + i][m]);
-                if constexpr (SPLIT_W) acc[i0 + i][m] = mfma16(a.l[m], f.h[i], acc[i0 + i][m]);
-                acc[i0 + i][m] = mfma16(a.h[m], f.h[i], acc[i0 + i][m]);
-            }
+        for (int m = 0; m < kRB; ++m) {
+            acc[m] = mfma16(a.h[m], f.l, acc[m]);
+            if constexpr (SPLIT_W) acc[m] = mfma16(a.l[m], f.h, acc[m]);
+            acc[m] = mfma16(a.h[m], f.h, acc[m]);
         }
     }
     // level buffer: T hi [kMixTM][SB] then T lo [kMixTM][SB], written once
@@ -328,54 +327,135 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
 
         // this wave's column blocks cb = wc + kWC i, i < ncb
         const int ncb = min(kCB, max(0, (nb - wc + kWC - 1) / kWC));
-        for (int s = B.slice_begin[j]; s < B.slice_begin[j + 1]; ++s) {
-            const MixSlice &ms = slices[s];
-            const uint32_t pos0 = (kstr * (uint32_t)B.rate[j] + (uint32_t)lo) & (uint32_t)(ms.capY - 1);
-            const void *ring = static_cast<const char *>(ms.Y) + (int64_t)it.det * ms.ydet * 4;
-            // columns past the window read its last sample (finite, never
-            // stored); the window (n <= capY, checked at plan time) is
-            // contiguous in the mirror ring, and the buffer range guards the rest
-            int pc[kCB];
+        // acc += H_up(level j+1), read from the LDS level buffer
+        auto upsample_level = [&]() {
+            if (j < B.nlev - 1) {
+                const int logp = B.shp[j + 1];
+                const float *taps = tp + B.up_off[j + 1];
+                const int n_prev = B.n[j + 1];
+                // for p <= 16 one kernel fragment serves every block of the level
+                const typename Op::KerF k0 = Op::ker(up_pos(lo, li, logp), nup, taps, lg);
 #pragma unroll
-            for (int i = 0; i < kCB; ++i) pc[i] = (int)pos0 + min((wc + kWC * i) * 16 + li, n - 1);
-            typename Op::Src src;
-            Op::init(src, ms, ring, it.r0 + rw, pc, li, lg);
-            // loads are unconditional: idle column blocks re-read the
-            // window's last sample (L1 hits)
-            for (int l0 = 0; l0 < ms.Lpad; l0 += Op::K) {
-                typename Op::FragA a;
-                typename Op::FragB b;
-                Op::load_a(a, src, l0);
-                Op::load_b(b, src, l0, 0);
-                Op::mma(acc, a, b, 0, ncb);
-                if (ncb > kCBH) {
-                    Op::load_b(b, src, l0, kCBH);
-                    Op::mma(acc, a, b, kCBH, ncb);
+                for (int i = 0; i < kCB; ++i) {
+                    const int cb = wc + kWC * i;
+                    if (cb >= nb) continue;   // wave-uniform
+                    const int i0 = lo + cb * 16;
+                    const int m0 = (i0 >> logp) - nup - lo_prev;
+                    if (logp <= 4) {
+                        Op::upsample(lvl, rw, m0, n_prev, logp, k0, li, lg, acc[i]);
+                    } else {
+                        const typename Op::KerF kb = Op::ker(up_pos(i0, li, logp), nup, taps, lg);
+                        Op::upsample(lvl, rw, m0, n_prev, logp, kb, li, lg, acc[i]);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);   // keep one block's LDS reads in flight at a time
                 }
             }
-        }
-        if (j < B.nlev - 1) {
-            const int logp = B.shp[j + 1];
-            const float *taps = tp + B.up_off[j + 1];
-            const int n_prev = B.n[j + 1];
-            // for p <= 16 one kernel fragment serves every block of the level
-            const typename Op::KerF k0 = Op::ker(up_pos(lo, li, logp), nup, taps, lg);
+        };
+        if constexpr (Op::STAGED) {
+            upsample_level();
+            __syncthreads();   // every wave is done reading level j+1: the buffer now stages y
+
+            // contraction over the chunks (slice s, basis rows l0 .. l0 + K) of
+            // level j.  Each chunk's y window (ncs columns, every group of the K
+            // rows, both planes) is copied by the work group from the ring into
+            // one of two LDS stages with asynchronous buffer-to-LDS loads, and
+            // each wave's W~ fragments are loaded into registers, one chunk ahead:
+            // per chunk one wait and one barrier, then the next chunk's copies
+            // and W~ loads go out before this chunk's MFMAs.
+            {
+                const int sb = B.slice_begin[j], se = B.slice_begin[j + 1];
+                const int ncs = min(kMixTN, (nb * 16 + 63) & ~63);   // staged columns
+                const int nq = ncs >> 6;                             // 64-column copies per plane and group
+                const int ncopy = Op::PLANES * 4 * nq;
+                const int stage_bytes = ncopy * 1024;                // <= LVL_BYTES / 2
+                const uint32_t rate = (uint32_t)B.rate[j];
+                auto issue = [&](int sl, int l0, int so, typename Op::FragA &fa) {
+                    const MixSlice &ms = slices[sl];
+                    const uint32_t cap2 = 2u * (uint32_t)ms.capY;
+                    const uint32_t pos0 = (kstr * rate + (uint32_t)lo) & (uint32_t)(ms.capY - 1);
+                    const char *ring = static_cast<const char *>(ms.Y) + (int64_t)it.det * ms.ydet * 4;
+                    const uint32_t plane = cap2 * (uint32_t)ms.Lpad * (16 / Op::RING_G);   // bytes per plane
+                    const __amdgpu_buffer_rsrc_t ry = buffer_rsrc(ring, plane * Op::PLANES);
+                    const int soff = (l0 / Op::RING_G) * (int)cap2 * 16;
+                    // columns past the window re-read its last sample (finite,
+                    // never stored): every copy stays inside the window, which is
+                    // contiguous in the mirror ring (n <= capY, checked at plan time)
+                    for (int q = wave; q < ncopy; q += 4) {
+                        const int pl = q / (4 * nq), kg = (q / nq) & 3, cq = q - (q / nq) * nq;
+                        const uint32_t c = (uint32_t)min(cq * 64 + lane, n - 1);
+                        const int voff = (int)(((uint32_t)kg * cap2 + pos0 + c) * 16u + pl * plane);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                            ry, (__attribute__((address_space(3))) void *)(lds + so + ((pl * 4 + kg) * ncs + cq * 64) * 16),
+                            16, voff, soff, 0, 0);
+                    }
+                    typename Op::ASrc as;
+                    Op::init_a(as, ms, it.r0 + rw, li, lg);
+                    Op::load_a(fa, as, l0);
+                };
+                int cs = sb, cl = 0, so = 0;
+                typename Op::FragA fa0, fa1;
+                if (sb < se) issue(cs, cl, so, fa0);
+                auto step = [&](const typename Op::FragA &fcur, typename Op::FragA &fnext) -> bool {
+                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this chunk's copies and W~ have landed
+                    __syncthreads();                      // ... for every wave; the other stage is free
+                    int ns = cs, nl = cl + Op::K;
+                    if (nl >= slices[ns].Lpad) {
+                        ++ns;
+                        nl = 0;
+                    }
+                    const bool more = ns < se;
+                    if (more) issue(ns, nl, so ^ stage_bytes, fnext);
+                    const char *st = lds + so;
 #pragma unroll
-            for (int i = 0; i < kCB; ++i) {
-                const int cb = wc + kWC * i;
-                if (cb >= nb) continue;   // wave-uniform
-                const int i0 = lo + cb * 16;
-                const int m0 = (i0 >> logp) - nup - lo_prev;
-                if (logp <= 4) {
-                    Op::upsample(lvl, rw, m0, n_prev, logp, k0, li, lg, acc[i]);
-                } else {
-                    const typename Op::KerF kb = Op::ker(up_pos(i0, li, logp), nup, taps, lg);
-                    Op::upsample(lvl, rw, m0, n_prev, logp, kb, li, lg, acc[i]);
-                }
-                __builtin_amdgcn_sched_barrier(0);   // keep one block's LDS reads in flight at a time
+                    for (int i = 0; i < kCB; ++i) {
+                        if (i >= ncb) break;   // wave-uniform
+                        typename Op::FragB b;
+                        Op::read_b(b, st, ncs, wc + kWC * i, li, lg);
+                        Op::mma(acc[i], fcur, b);
+                    }
+                    cs = ns;
+                    cl = nl;
+                    so ^= stage_bytes;
+                    return more;
+                };
+                if (sb < se)
+                    for (;;) {
+                        if (!step(fa0, fa1)) break;
+                        if (!step(fa1, fa0)) break;
+                    }
             }
+            __syncthreads();   // every wave is done reading the stages
+        } else {
+            // direct-load contraction: both operands straight into registers
+            for (int s = B.slice_begin[j]; s < B.slice_begin[j + 1]; ++s) {
+                const MixSlice &ms = slices[s];
+                const uint32_t pos0 = (kstr * (uint32_t)B.rate[j] + (uint32_t)lo) & (uint32_t)(ms.capY - 1);
+                const void *ring = static_cast<const char *>(ms.Y) + (int64_t)it.det * ms.ydet * 4;
+                // columns past the window read its last sample (finite, never
+                // stored); the window (n <= capY, checked at plan time) is
+                // contiguous in the mirror ring, and the buffer range guards the rest
+                int pc[kCB];
+#pragma unroll
+                for (int i = 0; i < kCB; ++i) pc[i] = (int)pos0 + min((wc + kWC * i) * 16 + li, n - 1);
+                typename Op::Src src;
+                Op::init(src, ms, ring, it.r0 + rw, pc, li, lg);
+                // loads are unconditional: idle column blocks re-read the
+                // window's last sample (L1 hits)
+                for (int l0 = 0; l0 < ms.Lpad; l0 += Op::K) {
+                    typename Op::FragA a;
+                    typename Op::FragB b;
+                    Op::load_a(a, src, l0);
+                    Op::load_b(b, src, l0, 0);
+                    Op::mma(acc, a, b, 0, ncb);
+                    if (ncb > kCBH) {
+                        Op::load_b(b, src, l0, kCBH);
+                        Op::mma(acc, a, b, kCBH, ncb);
+                    }
+                }
+            }
+            upsample_level();
+            __syncthreads();   // every wave is done reading level j+1
         }
-        __syncthreads();   // every wave is done reading level j+1
         if (j > 0) {
 #pragma unroll
             for (int i = 0; i < kCB; ++i) {
