@@ -77,3 +77,33 @@ def test_split_basis_output_rings(plan_cls, precision):
     err = np.abs(y_gpu - y_ref).max() / np.abs(y_ref).max()
     print(f"{precision} basis outputs: rel err {err:.3e}")
     assert err < EXPECT[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp16", "fp8_bf16"])
+def test_set_slice_matches_plan_creation(plan_cls, precision):
+    """lloid_set_slice converts a slice exactly as plan creation does in every
+    precision form (FP8: e4m3 rows and their per-vector scales), so replacing
+    the slices of a plan built for bank A by those of bank B gives the series
+    and peaks of a plan built for B, bit for bit."""
+    F = 4096
+    banks_a = _ragged_banks()
+    banks_b = []
+    g = np.random.default_rng([7, 5, 1])
+    for bank in banks_a:   # same shapes, other values
+        sl = [synth.Slice(s.rate, s.delay, g.standard_normal(s.basis.shape) / np.sqrt(s.basis.shape[1]),
+                          g.standard_normal(s.mixing.shape) / np.sqrt(s.mixing.shape[1])) for s in bank.slices]
+        banks_b.append(synth.Bank(bank.n_templates, sl))
+    x = synth.gaussian_strain(85, 2, 3 * F)
+    ref = plan_cls(banks_b, F, 2, precision, normalize=False)
+    z_ref, p_ref = run_gpu(ref, x, 0, 3)
+    plan = plan_cls(banks_a, F, 2, precision, normalize=False)
+    k = 0
+    for bank in banks_b:
+        for s in bank.slices:
+            plan.set_slice(k, torch.from_numpy(s.basis).cuda(), torch.from_numpy(s.mixing).cuda())
+            k += 1
+    z, p = run_gpu(plan, x, 0, 3)
+    for b in range(len(banks_b)):
+        assert np.array_equal(z[b], z_ref[b]), f"bank {b}"
+        for pa, pb in zip(p[b], p_ref[b]):
+            assert np.array_equal(pa.index, pb.index) and np.array_equal(pa.snr, pb.snr)
