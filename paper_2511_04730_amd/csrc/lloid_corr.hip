@@ -39,6 +39,10 @@ namespace lloid {
 
 constexpr int kCB = 4;   // column blocks per wave
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 constexpr float kFp8StrainScale = 8.0f;
 
 __device__ __forceinline__ uint32_t fp8_byte(float v) {
@@ -58,7 +62,7 @@ struct StrainRegs {
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = tid + 256 * i;
-            v[i] = e < lim ? it.ring[p0 + e] : 0.0f;   // mirror ring: p0 + e < 2 cap
+            v[i] = e < lim ? ld_global<float>(it.ring + p0 + e) : 0.0f;   // mirror ring: p0 + e < 2 cap
         }
     }
 };
@@ -73,7 +77,7 @@ struct CorrF32 {
     };
     static constexpr int PER = kCorrMB * 16 * (TK / 4) / 256;
     struct Regs {
-        float4 u[PER];
+        f32x4 u[PER];   // plain vector type: promoted to registers (HIP's float4 is not)
         StrainRegs<TK> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
@@ -82,7 +86,7 @@ struct CorrF32 {
             const int e = tid + 256 * i;
             const int r = e / (TK / 4), c4 = e % (TK / 4);
             if (r < it.mb * 16)
-                g.u[i] = *reinterpret_cast<const float4 *>(it.U + (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 4 * c4);
+                g.u[i] = ld_global<f32x4>(it.U + (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 4 * c4);
         }
         g.d.load(it, p0, tid);
     }
@@ -140,7 +144,7 @@ struct Corr16 {
     };
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
     struct Regs {
-        uint4 uh[PER], ul[SPLIT_U ? PER : 1];
+        u32x4 uh[PER], ul[SPLIT_U ? PER : 1];   // plain vector type: promoted to registers (HIP's uint4 is not)
         StrainRegs<TK> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
@@ -152,8 +156,8 @@ struct Corr16 {
             const int r = e / (TK / 8), c8 = e % (TK / 8);
             if (r < it.mb * 16) {
                 const int64_t o = (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 8 * c8;
-                g.uh[i] = *reinterpret_cast<const uint4 *>(gh + o);
-                if constexpr (SPLIT_U) g.ul[i] = *reinterpret_cast<const uint4 *>(gl + o);
+                g.uh[i] = ld_global<u32x4>(gh + o);
+                if constexpr (SPLIT_U) g.ul[i] = ld_global<u32x4>(gl + o);
             }
         }
         g.d.load(it, p0, tid);
@@ -164,8 +168,8 @@ struct Corr16 {
             const int e = tid + 256 * i;
             const int r = e / (TK / 8), c8 = e % (TK / 8);
             if (r < it.mb * 16) {
-                *reinterpret_cast<uint4 *>(&s.Uh[r * US + 8 * c8]) = g.uh[i];
-                if constexpr (SPLIT_U) *reinterpret_cast<uint4 *>(&s.Ul[r * US + 8 * c8]) = g.ul[i];
+                *reinterpret_cast<u32x4 *>(&s.Uh[r * US + 8 * c8]) = g.uh[i];
+                if constexpr (SPLIT_U) *reinterpret_cast<u32x4 *>(&s.Ul[r * US + 8 * c8]) = g.ul[i];
             }
         }
         // copy sft holds d[i + sft] at position i
@@ -231,7 +235,7 @@ struct Corr8 {
     };
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
     struct Regs {
-        uint2 u[PER];
+        u32x2 u[PER];
         StrainRegs<TK> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
@@ -241,7 +245,7 @@ struct Corr8 {
             const int e = tid + 256 * i;
             const int r = e / (TK / 8), c8 = e % (TK / 8);
             if (r < it.mb * 16)
-                g.u[i] = *reinterpret_cast<const uint2 *>(gu + (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 8 * c8);
+                g.u[i] = ld_global<u32x2>(gu + (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 8 * c8);
         }
         g.d.load(it, p0, tid);
     }
@@ -250,7 +254,7 @@ struct Corr8 {
         for (int i = 0; i < PER; ++i) {
             const int e = tid + 256 * i;
             const int r = e / (TK / 8), c8 = e % (TK / 8);
-            if (r < it.mb * 16) *reinterpret_cast<uint2 *>(&s.U[r * US + 8 * c8]) = g.u[i];
+            if (r < it.mb * 16) *reinterpret_cast<u32x2 *>(&s.U[r * US + 8 * c8]) = g.u[i];
         }
 #pragma unroll
         for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
@@ -295,7 +299,7 @@ struct Corr8 {
             }
         }
     }
-    static __device__ __forceinline__ float scale(const CorrItem &it, int row) { return it.uscale[it.r0 + row]; }
+    static __device__ __forceinline__ float scale(const CorrItem &it, int row) { return ld_global<float>(it.uscale + it.r0 + row); }
     using RingT = __bf16;   // the FP8 form mixes in BF16x3
 };
 

@@ -35,6 +35,14 @@ __device__ __forceinline__ V buffer_load16(__amdgpu_buffer_rsrc_t r, int voff, i
     return __builtin_bit_cast(V, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
 }
 
+// A load through a pointer known to address global memory (pointers read
+// from work tables are generic; flat loads also count against the LDS
+// counter, so their waits cover both).
+template <typename V>
+__device__ __forceinline__ V ld_global(const void *p) {
+    return *(const __attribute__((address_space(1))) V *)(p);
+}
+
 // Element (pos, l) of one plane of a basis-output ring and element (r, l) of
 // a mixing matrix in fragment order (layouts in MixSlice); G = 16 / element size.
 template <int G>
