@@ -65,6 +65,22 @@ __device__ __forceinline__ float ker_value(int k, int off, int ph, int nup, cons
     return (t >= 0 && t <= 2 * nup) ? taps[ph * kUpTaps + t] : 0.0f;
 }
 
+// b = the better of b and the candidate of the lane that DPP control CTRL
+// selects (a permutation within each row of 16 lanes; VALU only)
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ void reduce_dpp(PeakCand &b) {
+    PeakCand o;
+    o.p2 = __int_as_float(dpp_i<CTRL>(__float_as_int(b.p2)));
+    o.idx = dpp_i<CTRL>(b.idx);
+    o.re = __int_as_float(dpp_i<CTRL>(__float_as_int(b.re)));
+    o.im = __int_as_float(dpp_i<CTRL>(__float_as_int(b.im)));
+    if (better(o.p2, o.idx, b.p2, b.idx)) b = o;
+}
+
 // Polyphase position of lane column c of a block at level index i0 (the
 // block's first output): q0 = floor(i0/p), off = floor(i/p) - q0, ph = i mod p.
 // For p <= 16 a block start is a multiple of 16 past the level's window
@@ -496,15 +512,13 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     const float p2 = re * re + im * im;
                     if (better(p2, it.t0 + c, b.p2, b.idx)) b = PeakCand{p2, it.t0 + c, re, im};
                 }
-                // reduce over the 16 lanes of the row group
-                for (int off = 1; off < 16; off <<= 1) {
-                    PeakCand o;
-                    o.p2 = __shfl_xor(b.p2, off, 64);
-                    o.idx = __shfl_xor(b.idx, off, 64);
-                    o.re = __shfl_xor(b.re, off, 64);
-                    o.im = __shfl_xor(b.im, off, 64);
-                    if (better(o.p2, o.idx, b.p2, b.idx)) b = o;
-                }
+                // reduce over the 16 lanes of the row group: pairs, quads,
+                // half rows, rows (the order is total, so any butterfly gives
+                // the same candidate)
+                reduce_dpp<0xB1>(b);    // quad_perm 1, 0, 3, 2
+                reduce_dpp<0x4E>(b);    // quad_perm 2, 3, 0, 1
+                reduce_dpp<0x141>(b);   // row_half_mirror
+                reduce_dpp<0x140>(b);   // row_mirror
                 if (li == 0) wbest[wave][8 * m + 2 * lg + h] = b;
             }
         }
