@@ -59,8 +59,9 @@ def test_realistic_bank_reduced_precision(plan_cls, precision):
 @pytest.mark.parametrize("precision", ["bf16x3", "fp16"])
 def test_split_basis_output_rings(plan_cls, precision):
     """The 16-bit forms keep the basis outputs as hi + lo planes of a
-    time-major ring; read back through lloid_inspect they match the
-    oracle's correlate step to the form's precision."""
+    ring grouped by 16 bytes of outputs per position; read back through
+    lloid_inspect they match the oracle's correlate step to the form's
+    precision."""
     from oracle import lloid as O
     w = synth.config1()
     x = synth.workload_strain(w)
