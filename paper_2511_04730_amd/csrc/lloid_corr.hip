@@ -67,6 +67,24 @@ struct StrainRegs {
     }
 };
 
+// The window of W consecutive samples from STEP u on that thread u needs to
+// write positions STEP u .. STEP u + STEP - 1 of all 8 shifted copies as
+// whole 32-bit words (threads u >= DL / STEP hold nothing).
+template <int TK, int STEP, int W>
+struct StrainWin {
+    static constexpr int N = kCorrTQ + TK;
+    static constexpr int DL = kCorrTQ + TK + 8;
+    float v[W];
+    __device__ __forceinline__ void load(const CorrItem &it, int64_t p0, int tid) {
+        const int lim = min(N, it.ncols + TK);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const int e = STEP * tid + j;
+            v[j] = e < lim ? ld_global<float>(it.ring + p0 + e) : 0.0f;   // mirror ring: p0 + e < 2 cap
+        }
+    }
+};
+
 // ------------------------------------------------------------------ FP32
 struct CorrF32 {
     static constexpr int TK = 32;
@@ -145,7 +163,7 @@ struct Corr16 {
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
     struct Regs {
         u32x4 uh[PER], ul[SPLIT_U ? PER : 1];   // plain vector type: promoted to registers (HIP's uint4 is not)
-        StrainRegs<TK> d;
+        StrainWin<TK, 2, 9> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
         const T *gh = static_cast<const T *>(it.Uhi);
@@ -172,21 +190,20 @@ struct Corr16 {
                 if constexpr (SPLIT_U) *reinterpret_cast<u32x4 *>(&s.Ul[r * US + 8 * c8]) = g.ul[i];
             }
         }
-        // copy sft holds d[i + sft] at position i
+        // copy sft holds d[i + sft] at position i; thread u writes the
+        // positions 2u, 2u + 1 of every copy as one word per plane
+        if (tid < DL / 2) {
+            typedef T T2 __attribute__((ext_vector_type(2)));
+            T h[9], l[9];
 #pragma unroll
-        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
-            const int e = tid + 256 * k;
-            if (e >= StrainRegs<TK>::N) continue;
-            const float v = g.d.v[k];
-            const T h = (T)v;
-            const T l = (T)(v - (float)h);
+            for (int j = 0; j < 9; ++j) {
+                h[j] = (T)g.d.v[j];
+                l[j] = (T)(g.d.v[j] - (float)h[j]);
+            }
 #pragma unroll
             for (int sft = 0; sft < 8; ++sft) {
-                const int i = e - sft;
-                if (i >= 0) {
-                    s.Dh[sft * DL + i] = h;
-                    s.Dl[sft * DL + i] = l;
-                }
+                *reinterpret_cast<T2 *>(&s.Dh[sft * DL + 2 * tid]) = T2{h[sft], h[sft + 1]};
+                *reinterpret_cast<T2 *>(&s.Dl[sft * DL + 2 * tid]) = T2{l[sft], l[sft + 1]};
             }
         }
     }
@@ -236,7 +253,7 @@ struct Corr8 {
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
     struct Regs {
         u32x2 u[PER];
-        StrainRegs<TK> d;
+        StrainWin<TK, 4, 11> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
         const uint8_t *gu = static_cast<const uint8_t *>(it.Uhi);
@@ -256,21 +273,22 @@ struct Corr8 {
             const int r = e / (TK / 8), c8 = e % (TK / 8);
             if (r < it.mb * 16) *reinterpret_cast<u32x2 *>(&s.U[r * US + 8 * c8]) = g.u[i];
         }
+        // thread u writes positions 4u .. 4u + 3 of every copy as one word per plane
+        if (tid < DL / 4) {
+            uint32_t h[11], l[11];
 #pragma unroll
-        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
-            const int e = tid + 256 * k;
-            if (e >= StrainRegs<TK>::N) continue;
-            // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
-            const float v = fminf(fmaxf(g.d.v[k] * kFp8StrainScale, -448.0f), 448.0f);
-            const uint32_t h = fp8_byte(v);
-            const uint32_t l = fp8_byte(v - fp8_value(h));
+            for (int j = 0; j < 11; ++j) {
+                // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
+                const float v = fminf(fmaxf(g.d.v[j] * kFp8StrainScale, -448.0f), 448.0f);
+                h[j] = fp8_byte(v);
+                l[j] = fp8_byte(v - fp8_value(h[j]));
+            }
 #pragma unroll
             for (int sft = 0; sft < 8; ++sft) {
-                const int i = e - sft;
-                if (i >= 0) {
-                    s.Dh[sft * DL + i] = (uint8_t)h;
-                    s.Dl[sft * DL + i] = (uint8_t)l;
-                }
+                *reinterpret_cast<uint32_t *>(&s.Dh[sft * DL + 4 * tid]) =
+                    h[sft] | (h[sft + 1] << 8) | (h[sft + 2] << 16) | (h[sft + 3] << 24);
+                *reinterpret_cast<uint32_t *>(&s.Dl[sft * DL + 4 * tid]) =
+                    l[sft] | (l[sft + 1] << 8) | (l[sft + 2] << 16) | (l[sft + 3] << 24);
             }
         }
     }
