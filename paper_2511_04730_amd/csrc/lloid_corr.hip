@@ -253,7 +253,7 @@ struct Corr8 {
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
     struct Regs {
         u32x2 u[PER];
-        StrainWin<TK, 4, 11> d;
+        StrainRegs<TK> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
         const uint8_t *gu = static_cast<const uint8_t *>(it.Uhi);
@@ -273,22 +273,23 @@ struct Corr8 {
             const int r = e / (TK / 8), c8 = e % (TK / 8);
             if (r < it.mb * 16) *reinterpret_cast<u32x2 *>(&s.U[r * US + 8 * c8]) = g.u[i];
         }
-        // thread u writes positions 4u .. 4u + 3 of every copy as one word per plane
-        if (tid < DL / 4) {
-            uint32_t h[11], l[11];
+        // one byte per sample and copy: packing whole words here costs more
+        // VALU on fewer threads than the shared-word stores cost
 #pragma unroll
-            for (int j = 0; j < 11; ++j) {
-                // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
-                const float v = fminf(fmaxf(g.d.v[j] * kFp8StrainScale, -448.0f), 448.0f);
-                h[j] = fp8_byte(v);
-                l[j] = fp8_byte(v - fp8_value(h[j]));
-            }
+        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= StrainRegs<TK>::N) continue;
+            // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
+            const float v = fminf(fmaxf(g.d.v[k] * kFp8StrainScale, -448.0f), 448.0f);
+            const uint32_t h = fp8_byte(v);
+            const uint32_t l = fp8_byte(v - fp8_value(h));
 #pragma unroll
             for (int sft = 0; sft < 8; ++sft) {
-                *reinterpret_cast<uint32_t *>(&s.Dh[sft * DL + 4 * tid]) =
-                    h[sft] | (h[sft + 1] << 8) | (h[sft + 2] << 16) | (h[sft + 3] << 24);
-                *reinterpret_cast<uint32_t *>(&s.Dl[sft * DL + 4 * tid]) =
-                    l[sft] | (l[sft + 1] << 8) | (l[sft + 2] << 16) | (l[sft + 3] << 24);
+                const int i = e - sft;
+                if (i >= 0) {
+                    s.Dh[sft * DL + i] = (uint8_t)h;
+                    s.Dl[sft * DL + i] = (uint8_t)l;
+                }
             }
         }
     }
