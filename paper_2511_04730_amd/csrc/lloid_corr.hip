@@ -28,7 +28,12 @@
 //         kFp8StrainScale and split into two e4m3 parts; outputs are
 //         rescaled by uscale[l] = 2^-e_l / kFp8StrainScale.
 // The partial sums of a split go to part[l * f + c]; the reduction adds the
-// splits in a fixed order.
+// splits in a fixed order.  A slice with one split writes its outputs
+// straight into the basis-output ring instead (four consecutive basis
+// outputs of a sample per lane, inside one 16-byte group; hi and lo planes
+// for the 16-bit forms).  The prefetch registers use plain vector types:
+// HIP's uint4 / float4 are union-based structs that the compiler does not
+// promote to registers, which put them in scratch memory.
 #include <hip/hip_runtime.h>
 
 #include "lloid_device.h"
