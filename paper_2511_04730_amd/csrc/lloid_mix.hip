@@ -26,9 +26,10 @@
 // fragment order, the basis-output rings (and the stages) grouped by 16
 // bytes of outputs with consecutive positions adjacent (layouts in
 // MixSlice).  The 16-bit rings already hold y as hi + lo, split once when
-// they are written.  Each wave owns the column blocks
-// cb = wave, wave + 4, ... of the window and all four 16-row blocks, so
-// every y fragment it loads feeds four row blocks.
+// they are written.  The four waves split the tile 2 x 2: a wave owns the
+// four 16-row blocks of one half of the rows and the column blocks cb = wc,
+// wc + 2, ... of the window, so every y fragment it reads feeds four row
+// blocks and every W~ fragment up to eight column blocks.
 //
 // The polyphase upsample is a banded contraction into the same accumulator:
 // for the 16 output columns of a block starting at level index i0, with
@@ -40,9 +41,11 @@
 // Eq. (upsample)).  off <= 7 and 2 N_up <= 16, so a 24- (FP32) or 32-wide
 // (16-bit) window of prev holds every tap.  One LDS buffer holds a level
 // (FP32, or hi and lo planes split once when the level is written, so that
-// the 16-bit fragments are aligned vector reads).  A level first adds the
-// upsampled level j+1 into its accumulators, then (after a barrier) uses
-// the buffer for its y stages, and finally overwrites it with level j.
+// the 16-bit fragments are aligned vector reads).  In the 16-bit forms a
+// level first adds the upsampled level j+1 into its accumulators, then
+// (after a barrier) uses the buffer for its y stages, and finally
+// overwrites it with level j; the FP32 form contracts first and upsamples
+// after.
 #include <hip/hip_runtime.h>
 
 #include "lloid_device.h"
