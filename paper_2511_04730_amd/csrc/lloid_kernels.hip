@@ -71,12 +71,28 @@ __global__ __launch_bounds__(256) void down_kernel(const DownItem *__restrict__ 
     for (int t = threadIdx.x; t < ntap; t += blockDim.x) taps[t] = it.taps[t];
     for (int t = threadIdx.x; t < seg; t += blockDim.x) xs[lds_pad(t)] = it.xring[base + t];
     __syncthreads();
-    const int i = threadIdx.x;
-    if (i < it.chunk) {
-        float acc = 0.0f;
-        const int b = i * it.D;
+    // T = blockDim / chunk threads share an output (T = 4 for 64 outputs),
+    // thread part p < T summing the taps p, p + T, ...; the parts are added
+    // in order, so the result does not depend on scheduling
+    const int T = blockDim.x / it.chunk;
+    const int o = threadIdx.x % it.chunk, part = threadIdx.x / it.chunk;
+    float acc = 0.0f;
+    const int b = o * it.D;
+    if (T == 1) {
         for (int t = 0; t < ntap; ++t) acc = fmaf(taps[t], xs[lds_pad(b + t)], acc);
-        const int64_t pos = posmod(m_first + i, it.capd);
+    } else if (part < T) {
+        for (int t = part; t < ntap; t += T) acc = fmaf(taps[t], xs[lds_pad(b + t)], acc);
+    }
+    float *red = xs + lds_pad(seg);   // blockDim floats past the staged segment
+    if (T > 1) {
+        __syncthreads();
+        red[threadIdx.x] = acc;
+        __syncthreads();
+        if (part == 0)
+            for (int q = 1; q < T; ++q) acc += red[q * it.chunk + o];
+    }
+    if (part == 0) {
+        const int64_t pos = posmod(m_first + o, it.capd);
         it.dring[pos] = acc;
         it.dring[pos + it.capd] = acc;
     }

@@ -571,7 +571,7 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
             const int chunk = std::min(256, f);
             const int c = D * ndown;
             const int seg = (chunk - 1) * D + 2 * c + 1;
-            lds = std::max(lds, 2 * c + 1 + seg + (seg >> 5) + 1);
+            lds = std::max(lds, 2 * c + 1 + seg + (seg >> 5) + 1 + 256);   // + the partial sums
             for (int det = 0; det < ND; ++det)
                 for (int m0 = 0; m0 < f; m0 += chunk)
                     items.push_back(DownItem{xr.base + det * xr.det_stride, dr.base + det * dr.det_stride, dtaps[D],
