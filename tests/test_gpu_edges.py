@@ -3,7 +3,8 @@ FP64 oracle: one template / one basis vector / one tap, templates whose
 mixing rows are all zero (left unnormalised, output exactly zero), all-zero
 strain, the largest basis (160 vectors), the deepest supported decimation
 (factor 64, one 64x upsampling stage), a seven-level chain, an odd
-detector count, and a clean rejection beyond the decimation limit."""
+detector count, a top rate that is not a power of two (768 Hz), and a clean
+rejection beyond the decimation limit."""
 import numpy as np
 import pytest
 
@@ -39,30 +40,30 @@ def _bank(seed, M, slices):
     return synth.Bank(M, out)
 
 
-def _delays(rates, lengths_s):
+def _delays(rates, lengths_s, top=F):
     """Delays in slice samples: each slice starts where the previous one
     ends, and no earlier than the look-ahead plus the decimator half-length."""
     la = O.lookahead(sorted(set(rates), reverse=True))
     by_rate = dict(zip(sorted(set(rates), reverse=True), la))
     t, out = 0.0, []
     for r, T in zip(rates, lengths_s):
-        need = by_rate[r] + (O.N_DOWN if r < F else 0)
+        need = by_rate[r] + (O.N_DOWN if r < top else 0)
         d = max(int(np.ceil(t * r)), need)
         out.append(d)
         t = (d + T * r) / r
     return out
 
 
-def _check(plan_cls, banks, n_det, n_strides, seed, precision="fp32", tol=FP32_TOL):
-    x = synth.gaussian_strain(seed, n_det, n_strides * F)
-    plan = plan_cls(banks, F, n_det, precision)
+def _check(plan_cls, banks, n_det, n_strides, seed, precision="fp32", tol=FP32_TOL, top=F):
+    x = synth.gaussian_strain(seed, n_det, n_strides * top)
+    plan = plan_cls(banks, top, n_det, precision)
     z, pk = run_gpu(plan, x, 0, n_strides)
     for b, bank in enumerate(banks):
-        ref = run_oracle(bank, x, F, 0, n_strides)
+        ref = run_oracle(bank, x, top, 0, n_strides)
         eps = snr_error(z[b], ref)
         print(f"bank {b}: eps={eps:.3e}")
         assert eps <= tol
-        check_peaks(pk[b], ref, F, float(np.abs(z[b] - ref).max()))
+        check_peaks(pk[b], ref, top, float(np.abs(z[b] - ref).max()))
     return z, pk
 
 
@@ -110,6 +111,19 @@ def test_seven_level_chain(plan_cls):
     bank = _bank(6, 9, [(r, dd, max(1, int(T * r)), 6) for r, dd, T in zip(rates, d, lengths)])
     _check(plan_cls, [bank], 1, 4, 204)
     _check(plan_cls, [bank], 1, 4, 204, precision="fp16", tol=1e-3)
+
+
+def test_top_rate_not_a_power_of_two(plan_cls):
+    """Top rate 768 Hz (a multiple of 256, not a power of two): three mixing
+    tiles per stride and decimated strides of 384, 96 and 12 samples, the
+    last two sharing each output's taps among several threads."""
+    top = 768
+    rates = [768, 384, 96, 12]
+    lengths = [200 / 768, 300 / 384, 150 / 96, 40 / 12]
+    d = _delays(rates, lengths, top)
+    bank = _bank(8, 11, [(r, dd, max(1, int(round(T * r))), L) for r, dd, T, L in zip(rates, d, lengths, [8, 10, 6, 4])])
+    _check(plan_cls, [bank], 2, 6, 205, top=top)
+    _check(plan_cls, [bank], 2, 6, 205, precision="bf16x3", tol=1e-4, top=top)
 
 
 def test_decimation_beyond_the_limit_is_rejected(plan_cls):
