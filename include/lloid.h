@@ -238,9 +238,10 @@ lloid_status lloid_orthonormalize(double *U_dev, int32_t L, int32_t N, double *W
  *                    64..65536; default chosen at plan time: the longest
  *                    power of two from 8192 down to 512 that still yields
  *                    2048 items).  The partial planes are reallocated.
- *   LLOID_OPT_CORR_COLS   output columns per correlation work item (64, 128,
- *                    192 or 256; default 256, or 64 when 256-column items at
- *                    a 512-tap split would number fewer than 2048).
+ *   LLOID_OPT_CORR_COLS   output columns per correlation work item (a
+ *                    multiple of 64 up to 512; default 512, or 64 when
+ *                    512-column items at a 512-tap split would number fewer
+ *                    than 2048).
  *   LLOID_OPT_CORR_GROUP  consecutive correlation items kept on one XCD
  *                    (0..64; 0 = dispatch order; default 16).
  *   LLOID_OPT_MIX_GROUP   consecutive mixing items kept on one XCD

@@ -17,7 +17,7 @@ from __future__ import annotations
 
 from typing import Callable, Optional, Sequence
 
-DEFAULT_COLS = (64, 128, 256)
+DEFAULT_COLS = (64, 128, 256, 512)
 DEFAULT_SPLITS = (512, 1024, 2048, 4096, 8192)
 DEFAULT_CORR_GROUPS = (0, 8, 16, 32)
 DEFAULT_MIX_GROUPS = (0, 16, 32, 64, 128, 256)

@@ -5,11 +5,12 @@
 // as a dense contraction on MFMA: A = U (rows l, K = taps), B = the Hankel
 // window of the stream at the slice rate (K = taps, N = output columns).
 //
-// A work item is one slice and detector, up to kCorrMB x 16 basis rows, up
-// to kCorrTQ = 256 output columns and one split of the taps.  Its four
-// waves own the 16-column blocks cb = wave, wave + 4, ... of the item, so
-// every basis fragment a wave reads from LDS feeds up to four column blocks
-// (and every strain fragment up to kCorrMB row blocks).  Taps advance in
+// A work item is one slice and detector, up to kCorrMB x 16 = 64 basis
+// rows, up to kCorrTQ = 512 output columns and one split of the taps.  Its
+// four waves own the 16-column blocks cb = wave, wave + 4, ... of the item,
+// so every basis fragment a wave reads from LDS feeds up to eight column
+// blocks (and every strain fragment up to kCorrMB row blocks); the wide
+// item spreads each stage's basis tile and barriers over many columns.  Taps advance in
 // stages: the basis tile and the strain segment of the next stage are
 // fetched into registers while the current stage's MFMAs run from LDS.
 //
@@ -42,7 +43,7 @@
 
 namespace lloid {
 
-constexpr int kCB = 4;   // column blocks per wave
+constexpr int kCB = kCorrTQ / 64;   // column blocks per wave (four waves)
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
@@ -68,24 +69,6 @@ struct StrainRegs {
         for (int i = 0; i < PER; ++i) {
             const int e = tid + 256 * i;
             v[i] = e < lim ? ld_global<float>(it.ring + p0 + e) : 0.0f;   // mirror ring: p0 + e < 2 cap
-        }
-    }
-};
-
-// The window of W consecutive samples from STEP u on that thread u needs to
-// write positions STEP u .. STEP u + STEP - 1 of all 8 shifted copies as
-// whole 32-bit words (threads u >= DL / STEP hold nothing).
-template <int TK, int STEP, int W>
-struct StrainWin {
-    static constexpr int N = kCorrTQ + TK;
-    static constexpr int DL = kCorrTQ + TK + 8;
-    float v[W];
-    __device__ __forceinline__ void load(const CorrItem &it, int64_t p0, int tid) {
-        const int lim = min(N, it.ncols + TK);
-#pragma unroll
-        for (int j = 0; j < W; ++j) {
-            const int e = STEP * tid + j;
-            v[j] = e < lim ? ld_global<float>(it.ring + p0 + e) : 0.0f;   // mirror ring: p0 + e < 2 cap
         }
     }
 };
@@ -168,7 +151,7 @@ struct Corr16 {
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
     struct Regs {
         u32x4 uh[PER], ul[SPLIT_U ? PER : 1];   // plain vector type: promoted to registers (HIP's uint4 is not)
-        StrainWin<TK, 2, 9> d;
+        StrainRegs<TK> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
         const T *gh = static_cast<const T *>(it.Uhi);
@@ -195,20 +178,21 @@ struct Corr16 {
                 if constexpr (SPLIT_U) *reinterpret_cast<u32x4 *>(&s.Ul[r * US + 8 * c8]) = g.ul[i];
             }
         }
-        // copy sft holds d[i + sft] at position i; thread u writes the
-        // positions 2u, 2u + 1 of every copy as one word per plane
-        if (tid < DL / 2) {
-            typedef T T2 __attribute__((ext_vector_type(2)));
-            T h[9], l[9];
+        // copy sft holds d[i + sft] at position i
 #pragma unroll
-            for (int j = 0; j < 9; ++j) {
-                h[j] = (T)g.d.v[j];
-                l[j] = (T)(g.d.v[j] - (float)h[j]);
-            }
+        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
+            const int e = tid + 256 * k;
+            if (e >= StrainRegs<TK>::N) continue;
+            const float v = g.d.v[k];
+            const T h = (T)v;
+            const T l = (T)(v - (float)h);
 #pragma unroll
             for (int sft = 0; sft < 8; ++sft) {
-                *reinterpret_cast<T2 *>(&s.Dh[sft * DL + 2 * tid]) = T2{h[sft], h[sft + 1]};
-                *reinterpret_cast<T2 *>(&s.Dl[sft * DL + 2 * tid]) = T2{l[sft], l[sft + 1]};
+                const int i = e - sft;
+                if (i >= 0) {
+                    s.Dh[sft * DL + i] = h;
+                    s.Dl[sft * DL + i] = l;
+                }
             }
         }
     }
@@ -278,8 +262,7 @@ struct Corr8 {
             const int r = e / (TK / 8), c8 = e % (TK / 8);
             if (r < it.mb * 16) *reinterpret_cast<u32x2 *>(&s.U[r * US + 8 * c8]) = g.u[i];
         }
-        // one byte per sample and copy: packing whole words here costs more
-        // VALU on fewer threads than the shared-word stores cost
+        // one byte per sample and copy
 #pragma unroll
         for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
             const int e = tid + 256 * k;

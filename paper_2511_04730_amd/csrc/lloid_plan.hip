@@ -393,7 +393,7 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
     }
     P->series_floats = series_off;
 
-    // Correlation tiling: 256-column items and the longest tap split of
+    // Correlation tiling: 512-column items and the longest tap split of
     // 8192..512 that still gives at least 2048 work items (8 per CU); longer
     // splits write fewer partial planes for the reduction to read back.
     // Banks too small for that get 64-column items.

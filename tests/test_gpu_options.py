@@ -120,7 +120,7 @@ def test_option_values_are_checked(plan_cls):
     plan = plan_cls(_ragged_banks()[:1], F, 1, "fp32")
     for name, bad in [("corr_split", 0), ("corr_split", 100), ("corr_split", 65600), ("corr_group", -1),
                       ("corr_group", 65), ("mix_group", 257), ("graph", 2), ("corr_cols", 0),
-                      ("corr_cols", 100), ("corr_cols", 320)]:
+                      ("corr_cols", 100), ("corr_cols", 576)]:
         with pytest.raises(LloidError):
             plan.set_option(name, bad)
     opts = plan.options()
