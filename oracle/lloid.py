@@ -16,6 +16,7 @@ primitives:
                        "Upsampling SNR segments" / "Combining SNR segments",
                        recursion of the pre-synchronisation equation
   triggers          -- Sec. II.D.1: max |complex SNR| per template per window
+  xi^2              -- Sec. II.D.2: signal-consistency statistic at a trigger
 
 Readings of points the paper leaves open are stated where they are used:
 
@@ -47,6 +48,17 @@ Readings of points the paper leaves open are stated where they are used:
   template, with a separate flag for |z| >= 4.
 * R14 argmax ties resolve to the lowest index.
 * R15 history before the first sample and gap strides are zeros.
+* R20 the template autocorrelation R(t) of Sec. II.D.2 (normalised to
+  R(0) = 1) is sum_j h[j] conj h[j - t] / sum_j |h[j]|^2 for the complex
+  filter h = h_cos + i h_sin in tau order.  With z(t) = sum_j h[j] x[t - j]
+  (brute_force's convention) and white unit-variance strain this is
+  E[z(t) conj z(0)] / E|z(0)|^2, the choice that makes the xi^2 denominator
+  2 - 2|R|^2 the noise expectation of the numerator.
+* R21 the xi^2 integrals are sums over top-rate samples t = -delta..delta
+  (dt cancels), delta = (A - 1) / 2 for an autocorrelation of odd length A;
+  samples outside the available SNR are left out of both sums.
+* R22 xi^2 is evaluated at every per-stride peak (R13), with z(0) the SNR
+  at the peak index; the threshold flag is left to the caller.
 * normalisation: each real row is scaled so that sum_s sum_l W^s[r,l]^2 = 1
   (the reconstructed template has unit norm), computed in float64.
 """
@@ -458,3 +470,52 @@ def cholesky_qr2(U: np.ndarray, W: np.ndarray):
         U = np.linalg.solve(C, U)          # R^-T U
         W = W @ C                          # W R^T
     return U, W
+
+
+# ---------------------------------------------------------------------------
+# Signal-consistency statistic xi^2 (Sec. II.D.2)
+# ---------------------------------------------------------------------------
+
+def template_autocorrelation(h: np.ndarray, half_width: int) -> np.ndarray:
+    """R(t) for t = -half_width..half_width (index t + half_width) of the
+    complex templates h [..., n] in tau order, normalised to R(0) = 1
+    (reading R20): R(t) = sum_j h[j] conj h[j - t] / sum_j |h[j]|^2."""
+    h = np.asarray(h, np.complex128)
+    n = h.shape[-1]
+    power = np.sum(np.abs(h) ** 2, axis=-1)
+    out = np.zeros(h.shape[:-1] + (2 * half_width + 1,), np.complex128)
+    for t in range(-half_width, half_width + 1):
+        if abs(t) >= n:
+            continue
+        if t >= 0:                                   # j = t .. n-1
+            c = np.sum(h[..., t:] * np.conj(h[..., :n - t]), axis=-1)
+        else:                                        # j = 0 .. n-1+t
+            c = np.sum(h[..., :n + t] * np.conj(h[..., -t:]), axis=-1)
+        out[..., t + half_width] = c / power
+    return out
+
+
+def xi2(z: np.ndarray, t_peak: np.ndarray, R: np.ndarray) -> np.ndarray:
+    """xi^2 of Sec. II.D.2 for every row of z (complex [K, T], the SNR series
+    around the triggers), at index t_peak[k] of row k, with the
+    autocorrelation R [K, A] of that row's template (A odd):
+
+        num = sum_{t=-delta}^{delta} |z(t_p + t) - z(t_p) R(t)|^2
+        den = sum_{t=-delta}^{delta} (2 - 2 |R(t)|^2)
+
+    and xi^2 = num / den (reading R21: samples, not integrals; indices
+    t_p + t outside [0, T) are left out of both sums)."""
+    z = np.asarray(z, np.complex128)
+    R = np.asarray(R, np.complex128)
+    K, T = z.shape
+    A = R.shape[1]
+    assert A % 2 == 1 and R.shape[0] == K
+    delta = (A - 1) // 2
+    rows = np.arange(K)[:, None]
+    idx = np.asarray(t_peak, np.int64)[:, None] + np.arange(-delta, delta + 1)[None, :]
+    have = (idx >= 0) & (idx < T)
+    zt = np.where(have, z[rows, np.clip(idx, 0, T - 1)], 0.0)
+    z0 = z[np.arange(K), np.asarray(t_peak, np.int64)][:, None]
+    num = np.sum(np.where(have, np.abs(zt - z0 * R) ** 2, 0.0), axis=1)
+    den = np.sum(np.where(have, 2.0 - 2.0 * np.abs(R) ** 2, 0.0), axis=1)
+    return num / den
