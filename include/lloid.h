@@ -267,17 +267,54 @@ typedef enum {
 } lloid_option;
 lloid_status lloid_set_option(lloid_plan *plan, int32_t option, int64_t value);
 
+/* Signal-consistency statistic xi^2 at the triggers (Sec. II.D.2):
+ *   xi^2 = sum_t |z(t_p + t) - z(t_p) R(t)|^2 / sum_t (2 - 2 |R(t)|^2),
+ *   t = -delta..delta (top-rate samples), delta = (A - 1) / 2,
+ * for the complex SNR z of one template and detector around its trigger
+ * index t_p, with R the template's complex autocorrelation, normalised to
+ * R(0) = 1 and oriented so that E[z(t) conj z(0)] = 2 R(t) in white noise:
+ * R(t) = sum_j h[j] conj h[j - t] / sum_j |h[j]|^2 for the complex filter
+ * h = h_cos + i h_sin indexed by time before merger.
+ *
+ * lloid_set_autocorrelation stores the autocorrelations, stacked across the
+ * plan's banks (Sec. II.D.2).
+ *   acf_dev   device, float64: for every bank b in order, its block
+ *             [M_b][A_b][2] of (re, im) R_i(t), t = -delta_b..delta_b
+ *   acf_len   host [n_banks]: A_b, odd, 3 <= A_b <= 2 F + 1
+ * They are converted to float32 in plan-owned memory (replacing earlier
+ * ones); the caller may free acf_dev on return.  Synchronises `stream`.
+ * Errors: LLOID_E_ARG, LLOID_E_SHAPE (an even, too short or too long A_b),
+ * LLOID_E_NOMEM, LLOID_E_HIP.
+ *
+ * lloid_xi2 computes xi^2 at every trigger of stride k (trigger window =
+ * the stride; the threshold flag is left to the caller).
+ *   prev_dev, cur_dev, next_dev  device series of strides k - 1, k, k + 1
+ *             as lloid_push_stride writes them (cur_dev required).  prev or
+ *             next may be NULL (first or last stride of the data): samples
+ *             there are left out of both sums.  With next_dev given, call
+ *             after stride k + 1 has been filtered (delta samples of latency).
+ *   peaks_dev device, the triggers of stride k (lloid_push_stride)
+ *   xi2_dev   device float32 [LLOID_Q_N_PEAKS], entry for entry with the
+ *             triggers; NaN where a trigger index lies outside the stride.
+ * Errors: LLOID_E_ARG (NULL cur, peaks or output), LLOID_E_STATE (no
+ * autocorrelations stored), LLOID_E_HIP. */
+lloid_status lloid_set_autocorrelation(lloid_plan *plan, const double *acf_dev, const int32_t *acf_len,
+                                       void *stream);
+lloid_status lloid_xi2(lloid_plan *plan, const float *prev_dev, const float *cur_dev, const float *next_dev,
+                       const lloid_peak *peaks_dev, float *xi2_dev, void *stream);
+
 /* Per-kernel timing of lloid_push_stride with HIP events recorded on the
  * call's stream around each of the stride's kernels:
  *   0 ingest, 1 decimation, 2 basis correlation, 3 split reduction,
- *   4 mixing + upsample-and-add + series + peak candidates, 5 triggers.
+ *   4 mixing + upsample-and-add + series + peak candidates, 5 triggers,
+ *   and 6 xi^2 for lloid_xi2.
  * lloid_profile_enable(plan, 1) starts a new accumulation (0 stops it);
  * lloid_profile_read synchronises the recorded events and returns the
  * summed duration (ms) and the number of launches of one kernel since the
  * accumulation started.  Errors: LLOID_E_ARG, LLOID_E_HIP. */
 typedef enum {
     LLOID_K_INGEST = 0, LLOID_K_DOWN = 1, LLOID_K_CORR = 2,
-    LLOID_K_REDUCE = 3, LLOID_K_MIX = 4, LLOID_K_PEAKS = 5, LLOID_K_COUNT = 6
+    LLOID_K_REDUCE = 3, LLOID_K_MIX = 4, LLOID_K_PEAKS = 5, LLOID_K_XI2 = 6, LLOID_K_COUNT = 7
 } lloid_kernel_id;
 lloid_status lloid_profile_enable(lloid_plan *plan, int32_t enable);
 lloid_status lloid_profile_read(lloid_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);

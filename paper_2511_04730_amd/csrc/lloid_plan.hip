@@ -109,6 +109,12 @@ struct lloid_plan {
     int64_t *d_stride = nullptr;
     int64_t series_floats = 0, n_peaks = 0, total_templates = 0;
 
+    // xi^2: per-template table and float32 autocorrelations (lloid_set_autocorrelation)
+    XiTemplate *d_xitab = nullptr;
+    float *d_acf = nullptr;
+    int32_t n_xi = 0;
+    size_t xi_bytes = 0;
+
     // graph mode (LLOID_OPT_GRAPH)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;
@@ -1234,6 +1240,60 @@ lloid_status lloid_set_slice(lloid_plan *P, int32_t slice, const double *U, cons
         }
     }
     HIP_OK(hipStreamSynchronize(st));
+    return LLOID_OK;
+}
+
+lloid_status lloid_set_autocorrelation(lloid_plan *P, const double *acf, const int32_t *acf_len, void *stream) {
+    if (!P || !acf || !acf_len) return LLOID_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::vector<XiTemplate> tab;
+    tab.reserve((size_t)P->total_templates);
+    int64_t floats = 0;
+    for (size_t b = 0; b < P->banks.size(); ++b) {
+        const int A = acf_len[b];
+        if (A < 3 || A % 2 == 0 || A > 2 * P->F + 1) return LLOID_E_SHAPE;
+        const PBank &pb = P->banks[b];
+        for (int m = 0; m < pb.M; ++m) {
+            XiTemplate e{};
+            e.series_off = pb.series_off + (int64_t)m * P->F * 2;
+            e.det_stride = (int64_t)pb.M * P->F * 2;
+            e.peak_off = pb.peak_off + m;
+            e.acf_off = floats;
+            e.A = A;
+            e.M = pb.M;
+            tab.push_back(e);
+            floats += 2 * (int64_t)A;
+        }
+    }
+    // drop earlier autocorrelations (hipFree waits for work that uses them)
+    P->release(P->d_acf);
+    P->release(P->d_xitab);
+    P->device_bytes -= P->xi_bytes;
+    P->d_acf = nullptr;
+    P->d_xitab = nullptr;
+    P->n_xi = 0;
+    const size_t before = P->device_bytes;
+    float *acf32 = nullptr;
+    XiTemplate *xtab = nullptr;
+    ST_OK(P->alloc(&acf32, (size_t)floats, false));
+    ST_OK(upload(P, &xtab, tab, st));
+    HIP_OK(launch_convert_f64_f32(st, acf, floats, acf32));
+    HIP_OK(hipStreamSynchronize(st));
+    P->xi_bytes = P->device_bytes - before;
+    P->d_acf = acf32;
+    P->d_xitab = xtab;
+    P->n_xi = (int32_t)tab.size();
+    return LLOID_OK;
+}
+
+lloid_status lloid_xi2(lloid_plan *P, const float *prev, const float *cur, const float *next, const lloid_peak *peaks,
+                       float *out, void *stream) {
+    if (!P || !cur || !peaks || !out) return LLOID_E_ARG;
+    if (!P->d_xitab) return LLOID_E_STATE;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_OK(P->mark(LLOID_K_XI2, st, true));
+    HIP_OK(launch_xi2(st, P->d_xitab, P->n_xi, P->n_det, P->F, prev, cur, next, peaks, P->d_acf, out));
+    HIP_OK(P->mark(LLOID_K_XI2, st, false));
     return LLOID_OK;
 }
 

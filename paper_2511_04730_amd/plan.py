@@ -153,6 +153,36 @@ class LloidPlan:
         return PeakArrays(f[:, 0].reshape(shp).copy(), raw[:, 1].reshape(shp).copy(), f[:, 2].reshape(shp).copy(),
                           f[:, 3].reshape(shp).copy(), raw[:, 4].reshape(shp).copy())
 
+    # ------------------------------------------------------------ xi^2
+    def set_autocorrelation(self, acf, lengths, stream=None) -> None:
+        """Store the template autocorrelations for xi2(): acf is a cuda
+        float64 tensor holding, bank after bank, [M_b, A_b, 2] blocks of
+        (re, im) R(t), t = -(A_b-1)/2 .. (A_b-1)/2; lengths = [A_b]."""
+        import torch
+        assert acf.is_cuda and acf.dtype == torch.float64 and acf.is_contiguous()
+        A = (ctypes.c_int32 * self.n_banks)(*[int(a) for a in lengths])
+        assert acf.numel() == sum(2 * M * a for M, a in zip(self.bank_templates, lengths))
+        L.check(self.lib.lloid_set_autocorrelation(self.handle, ctypes.c_void_p(acf.data_ptr()), A,
+                                                   _stream_handle(stream)), "lloid_set_autocorrelation")
+
+    def xi2(self, cur, peaks, prev=None, next=None, out=None, stream=None):
+        """xi^2 at the triggers `peaks` of the stride whose series is `cur`
+        (prev / next: the neighbouring strides' series, or None).  Returns a
+        cuda float32 tensor [n_peaks], in the order of the triggers."""
+        import torch
+        if out is None:
+            out = torch.empty(self.n_peaks, dtype=torch.float32, device="cuda")
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None)
+        L.check(self.lib.lloid_xi2(self.handle, ptr(prev), ptr(cur), ptr(next), ptr(peaks), ptr(out),
+                                   _stream_handle(stream)), "lloid_xi2")
+        return out
+
+    def xi2_view(self, xi2, bank: int) -> "np.ndarray":
+        """Host array [n_det, M_b] of one bank's xi^2 values."""
+        M = self.bank_templates[bank]
+        off = self.bank_peak_offset[bank]
+        return xi2[off:off + self.n_detectors * M].cpu().numpy().reshape(self.n_detectors, M)
+
     # ------------------------------------------------------------ gradient
     def slice_shapes(self):
         """(2M, L, N) of every slice, banks in order."""

@@ -332,6 +332,32 @@ def random_subbank(g: np.random.Generator, top_rate: int, n_rates_range: Tuple[i
 
 
 # ---------------------------------------------------------------------------
+# Autocorrelation inputs of the xi^2 statistic (seeded stand-ins)
+# ---------------------------------------------------------------------------
+
+ACF_SHORT, ACF_LONG = 351, 701   # full autocorrelation lengths for high- and low-mass templates
+
+
+def acf_length(bank: Bank) -> int:
+    """ACF_SHORT for banks whose templates last at most 8 s, ACF_LONG beyond."""
+    dur = max((s.delay + s.basis.shape[1]) / s.rate for s in bank.slices)
+    return ACF_LONG if dur > 8.0 else ACF_SHORT
+
+
+def synthetic_acf(config: int, index: int, n_templates: int, length: int) -> np.ndarray:
+    """Seeded chirp-like autocorrelations, complex [M, length], t = -(length-1)/2
+    .. (length-1)/2: R(t) = exp(-(t/w)^2/2) exp(-i (a t + b t |t|)) with
+    per-template width w, frequency a and sweep b.  R(0) = 1, |R| <= 1 and
+    R(-t) = conj R(t), as for a template's own autocorrelation."""
+    g = rng_for(config, PURPOSE_STRUCT, 1000 + index)
+    t = np.arange(length) - (length - 1) // 2
+    w = g.uniform(5.0, 60.0, n_templates)[:, None]
+    a = g.uniform(0.05, 1.5, n_templates)[:, None]
+    b = g.uniform(-2e-3, 2e-3, n_templates)[:, None]
+    return np.exp(-0.5 * (t / w) ** 2) * np.exp(-1j * (a * t + b * t * np.abs(t)))
+
+
+# ---------------------------------------------------------------------------
 # Strain and injections
 # ---------------------------------------------------------------------------
 

@@ -1,0 +1,211 @@
+"""GPU parity of the xi^2 statistic (Sec. II.D.2) through the C ABI against
+the FP64 oracle.
+
+* kernel parity on seeded synthetic series, triggers and autocorrelations
+  (both sides get the same inputs), for every combination of neighbouring
+  strides given or absent, autocorrelation lengths from 3 to 2 F + 1 (the
+  window then spans the whole previous and next stride), triggers at the
+  stride's edges, three ragged banks and two detectors;
+* the same at the size of the 1024-template realistic bank with 701-sample
+  autocorrelations;
+* end to end: GPU series and triggers of a chirp bank with an injected
+  signal against the oracle's series, triggers and xi^2 (where the trigger
+  indices agree);
+* argument and state errors.
+
+Tolerance: each lane of the FP32 kernel adds A / 64 terms, a wave tree adds
+six more levels, and each term carries a few roundings (including R's
+conversion to FP32).  With c = (A / 64 + 16) 2^-24, S = sum (|z| + |z0| |R|)^2
+and D = sum (2 + 2 |R|^2) over the window, the numerator is off by at most
+c S and the denominator by c D, so
+    |xi2_gpu - xi2| <= c (S + xi2 D) / den
+to first order.  S / den is itself an xi^2: that of |z| against -|R|.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import lloid as O
+
+from lloid_check import run_oracle
+from test_gpu_parity import _ragged_banks
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+F = 4096
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def plan_cls():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_04730_amd import LloidPlan
+    return LloidPlan
+
+
+def _acf_tensor(acfs):
+    """Stack per-bank complex [M_b, A_b] arrays into the float64 device layout."""
+    parts = [np.stack([R.real, R.imag], axis=-1).reshape(-1) for R in acfs]
+    return torch.from_numpy(np.ascontiguousarray(np.concatenate(parts))).cuda()
+
+
+def _synthetic_series(plan, seed, n):
+    g = synth.rng_for(97, synth.PURPOSE_NOISE, seed)
+    return [torch.from_numpy((3.0 * g.standard_normal(plan.series_floats)).astype(np.float32)).cuda()
+            for _ in range(n)]
+
+
+def _synthetic_peaks(plan, seed, deltas):
+    """Trigger entries with only the index set: random, plus the stride's
+    edges and the points where the window starts to leave the stride."""
+    g = synth.rng_for(97, synth.PURPOSE_STRUCT, seed)
+    raw = np.zeros((plan.n_peaks, 5), np.int32)
+    for b in range(plan.n_banks):
+        M, off, d = plan.bank_templates[b], plan.bank_peak_offset[b], deltas[b]
+        idx = g.integers(0, F, plan.n_detectors * M)
+        special = [0, 1, F - 1, F - 2, min(d, F - 1), max(F - 1 - d, 0), min(d - 1, F - 1) if d > 0 else 0]
+        idx[:len(special)] = special[:len(idx)]
+        raw[off:off + plan.n_detectors * M, 1] = idx
+    return torch.from_numpy(raw.reshape(-1)).cuda(), raw[:, 1]
+
+
+def _oracle_xi2(plan, b, series, idx_all, R, have_prev, have_next):
+    """Oracle xi^2 and the rounding bound for bank b: rows [n_det M]."""
+    M, nd = plan.bank_templates[b], plan.n_detectors
+    rows = []
+    for which, s in zip(("prev", "cur", "next"), series):
+        if (which == "prev" and not have_prev) or (which == "next" and not have_next):
+            continue
+        rows.append(plan.bank_view(s, b).cpu().numpy().astype(np.complex128).reshape(nd * M, F))
+    z = np.concatenate(rows, axis=1)
+    off = plan.bank_peak_offset[b]
+    tp = idx_all[off:off + nd * M].astype(np.int64) + (F if have_prev else 0)
+    RR = np.tile(R, (nd, 1))
+    ref = O.xi2(z, tp, RR)
+    return ref.reshape(nd, M), _bound(z, tp, RR, ref).reshape(nd, M)
+
+
+def _bound(z, tp, RR, ref):
+    """Rounding bound c (S + xi2 D) / den of the module docstring."""
+    A = RR.shape[1]
+    d = (A - 1) // 2
+    have = (tp[:, None] + np.arange(-d, d + 1)[None, :] >= 0) & (tp[:, None] + np.arange(-d, d + 1)[None, :] < z.shape[1])
+    den = np.sum(np.where(have, 2.0 - 2.0 * np.abs(RR) ** 2, 0.0), axis=1)
+    D = np.sum(np.where(have, 2.0 + 2.0 * np.abs(RR) ** 2, 0.0), axis=1)
+    c = (A / 64 + 16) * U32
+    return c * (O.xi2(np.abs(z), tp, -np.abs(RR)) + ref * D / den)
+
+
+def _check_bank(plan, b, got, ref, bound):
+    g = plan.xi2_view(got, b)
+    err = np.abs(g - ref)
+    worst = float((err / np.maximum(bound, 1e-30)).max())
+    print(f"bank {b}: max |xi2 err| = {err.max():.3e}, worst err / bound = {worst:.3f}")
+    assert np.all(np.isfinite(g)) and np.all(err <= bound)
+
+
+@pytest.mark.parametrize("have_prev,have_next", [(True, True), (False, True), (True, False), (False, False)])
+def test_kernel_matches_oracle_on_synthetic_inputs(plan_cls, have_prev, have_next):
+    banks = _ragged_banks()
+    plan = plan_cls(banks, F, 2, "fp32")
+    lengths = [3, 701, 2 * F + 1]
+    acfs = [synth.synthetic_acf(97, b, plan.bank_templates[b], A) for b, A in enumerate(lengths)]
+    plan.set_autocorrelation(_acf_tensor(acfs), lengths)
+    series = _synthetic_series(plan, 1, 3)
+    peaks, idx = _synthetic_peaks(plan, 2, [(A - 1) // 2 for A in lengths])
+    got = plan.xi2(series[1], peaks, prev=series[0] if have_prev else None, next=series[2] if have_next else None)
+    torch.cuda.synchronize()
+    for b in range(plan.n_banks):
+        ref, bound = _oracle_xi2(plan, b, series, idx, acfs[b], have_prev, have_next)
+        _check_bank(plan, b, got, ref, bound)
+
+
+def test_out_of_stride_trigger_index_gives_nan(plan_cls):
+    banks = _ragged_banks()
+    plan = plan_cls(banks, F, 1, "fp32")
+    lengths = [351, 351, 351]
+    acfs = [synth.synthetic_acf(97, b, plan.bank_templates[b], A) for b, A in enumerate(lengths)]
+    plan.set_autocorrelation(_acf_tensor(acfs), lengths)
+    series = _synthetic_series(plan, 3, 1)
+    raw = np.zeros((plan.n_peaks, 5), np.int32)
+    raw[:, 1] = 100
+    raw[0, 1] = F
+    raw[1, 1] = -1
+    got = plan.xi2(series[0], torch.from_numpy(raw.reshape(-1)).cuda()).cpu().numpy()
+    assert np.isnan(got[0]) and np.isnan(got[1]) and np.all(np.isfinite(got[2:]))
+
+
+@pytest.fixture(scope="module")
+def c2():
+    return synth.cached_workload("c2", synth.config2)
+
+
+def test_realistic_bank_size(plan_cls, c2):
+    """1024 templates, 701-sample autocorrelations, all triggers."""
+    plan = plan_cls(c2.banks, c2.sample_rate, 1, "bf16x3")
+    A = synth.ACF_LONG
+    acf = synth.synthetic_acf(98, 0, plan.bank_templates[0], A)
+    plan.set_autocorrelation(_acf_tensor([acf]), [A])
+    series = _synthetic_series(plan, 4, 3)
+    peaks, idx = _synthetic_peaks(plan, 5, [(A - 1) // 2])
+    got = plan.xi2(series[1], peaks, prev=series[0], next=series[2])
+    torch.cuda.synchronize()
+    ref, bound = _oracle_xi2(plan, 0, series, idx, acf, True, True)
+    _check_bank(plan, 0, got, ref, bound)
+
+
+def test_end_to_end_against_oracle_series(plan_cls):
+    """Chirp bank, one injected template; xi^2 of stride 2's triggers from the
+    GPU's own series (strides 1..3) against the oracle's."""
+    bank = synth.chirp_bank(F, 24, 30.0, (1.0, 2.0), [(4096, 0.0, 1024, 24), (1024, 0.25, 1800, 30)],
+                            seed=[96, 1, 0], keep_templates=True)
+    x = synth.gaussian_strain(96, 1, 4 * F)
+    synth.inject(x, F, bank, synth.Injection(0, 5, 0, 2 * F + 1234, 12.0))
+    h = synth.full_rate_templates(bank, F)
+    A = synth.ACF_SHORT
+    d = (A - 1) // 2
+    R = O.template_autocorrelation(h[0::2] + 1j * h[1::2], d)
+
+    plan = plan_cls([bank], F, 1, "fp32")
+    plan.set_autocorrelation(_acf_tensor([R]), [A])
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    series, peaks = [], None
+    for k in range(4):
+        s, p = plan.push(xs[:, k * F:(k + 1) * F].contiguous())
+        series.append(s)
+        if k == 2:
+            peaks = p
+    got = plan.xi2_view(plan.xi2(series[2], peaks, prev=series[1], next=series[3]), 0)[0]
+    gidx = plan.peaks_view(peaks, 0).index[0]
+
+    zr = run_oracle(bank, x, F, 1, 3)[0]                   # strides 1..3, [M, 3F]
+    pr = O.window_peaks(zr[:, F:2 * F])
+    ref = O.xi2(zr, pr.index + F, R)
+    zg = np.concatenate([plan.bank_view(s, 0)[0].cpu().numpy().astype(np.complex128) for s in series[1:4]], axis=1)
+    e = float(np.abs(zg - zr).max())
+    den = np.sum(2.0 - 2.0 * np.abs(R) ** 2, axis=1)
+    sq = 4.0 * A * e * e
+    bound = (2.0 * np.sqrt(ref * den * sq) + sq) / den + _bound(zr, pr.index + F, R, ref)
+    same = gidx == pr.index
+    print(f"series e_abs={e:.3e}; indices agree for {same.sum()} of {len(same)}; "
+          f"injected template xi2 gpu={got[5]:.4f} oracle={ref[5]:.4f}")
+    assert same.mean() >= 0.9 and same[5]
+    assert np.all(np.abs(got[same] - ref[same]) <= bound[same])
+
+
+def test_errors(plan_cls):
+    from paper_2511_04730_amd._lib import LloidError
+    banks = _ragged_banks()
+    plan = plan_cls(banks, F, 1, "fp32")
+    series = _synthetic_series(plan, 6, 1)[0]
+    peaks = plan.new_peaks()
+    with pytest.raises(LloidError) as e:
+        plan.xi2(series, peaks)
+    assert e.value.status == -6          # LLOID_E_STATE: no autocorrelations
+    for bad in ([351, 350, 351], [351, 1, 351], [351, 351, 2 * F + 3]):
+        acfs = [synth.synthetic_acf(97, b, plan.bank_templates[b], A) for b, A in enumerate(bad)]
+        with pytest.raises(LloidError) as e:
+            plan.set_autocorrelation(_acf_tensor(acfs), bad)
+        assert e.value.status == -2      # LLOID_E_SHAPE
