@@ -137,15 +137,6 @@ struct PeakItem {
     int32_t M, n_ttiles;
 };
 
-// xi^2 (Sec. II.D.2): one entry per template, banks in order.
-struct XiTemplate {
-    int64_t series_off;      // float offset of detector 0's series of this template
-    int64_t det_stride;      // floats between detectors (M F 2)
-    int64_t peak_off;        // entry of detector 0's trigger (and its xi^2 output)
-    int64_t acf_off;         // float offset of the template's R(t), t = -delta..delta, (re, im)
-    int32_t A, M;            // autocorrelation length (odd); templates of the bank
-};
-
 // ---------------------------------------------------------------- launches
 struct LaunchCtx {
     hipStream_t stream;
@@ -175,13 +166,6 @@ hipError_t launch_convert_fp8_rows(hipStream_t, const double *src, int32_t rows,
 // as float rows dst[r * dst_ld + dst_off + c]
 hipError_t launch_ring_gather(hipStream_t, int precision, const void *ring, int32_t Lpad, int32_t cap, int64_t a,
                               int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off);
-
-// xi^2 at the triggers of one stride, and the float64 -> float32 copy of the
-// autocorrelations (lloid_xi2.hip)
-hipError_t launch_xi2(hipStream_t, const XiTemplate *tab, int32_t n_tmpl, int32_t n_det, int32_t F,
-                      const float *prev, const float *cur, const float *next, const lloid_peak *peaks,
-                      const float *acf, float *out);
-hipError_t launch_convert_f64_f32(hipStream_t, const double *src, int64_t n, float *dst);
 
 // gradient and re-orthonormalisation (lloid_grad.hip)
 hipError_t launch_copy_window(hipStream_t, const float *ring, int64_t ring_ld, int32_t cap, int64_t a,

@@ -18,6 +18,7 @@
 #include <vector>
 
 #include "lloid_internal.h"
+#include "lloid_xi2.h"
 
 using namespace lloid;
 

@@ -19,6 +19,7 @@
 
 #include "lloid_device.h"
 #include "lloid_internal.h"
+#include "lloid_xi2.h"
 
 namespace lloid {
 namespace {
