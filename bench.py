@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "template SNR-samples/sec per MI355X, batched BF16 vs plain FP32 at SNR err≤1e-3"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "fp16": 2500.0, "fp8_bf16": 5000.0}
+HBM_GBS = 8000.0   # MI355X HBM3E peak
 
 
 def kernel_peak(precision: str, kernel: str) -> float:
@@ -64,7 +65,8 @@ def workload(name: str):
 
 
 KERNEL_SOURCES = {"mix": ["lloid_mix.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
-                  "corr": ["lloid_corr.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"]}
+                  "corr": ["lloid_corr.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
+                  "xi2": ["lloid_xi2.hip", "lloid_xi2.h", "lloid_internal.h", "lloid_device.h"]}
 
 
 def source_digest(kernel: str) -> str:
@@ -136,6 +138,47 @@ def timed(plan, strides, warmup: int, steps: int, write: bool, profile: bool):
     return ms, prof
 
 
+def xi2_measure(plan, w, strides, reps: int):
+    """xi^2 (Sec. II.D.2) at the triggers of stride 1, from the series of
+    strides 0..2 of every bank and detector, with seeded chirp-like
+    autocorrelations of 351 or 701 samples per bank.  Returns a dict with
+    the mean duration of one launch (HIP events over `reps` launches) and
+    its algorithmic HBM bytes: per trigger the A-sample complex window, the
+    trigger entry and the output; per template its autocorrelation."""
+    import numpy as np
+    import torch
+    import synth
+    lengths = [synth.acf_length(b) for b in w.banks]
+    parts = []
+    for b, (bank, A) in enumerate(zip(w.banks, lengths)):
+        R = synth.synthetic_acf(w.config, b, bank.n_templates, A)
+        parts.append(np.stack([R.real, R.imag], axis=-1).reshape(-1))
+    acf = torch.from_numpy(np.concatenate(parts)).cuda()
+    del parts
+    plan.set_autocorrelation(acf, lengths)
+    del acf
+    plan.reset()
+    ser = [plan.new_series() for _ in range(3)]
+    pk = [plan.new_peaks() for _ in range(3)]
+    for k in range(3):
+        plan.push(strides[k], series=ser[k], peaks=pk[k])
+    out = torch.empty(plan.n_peaks, dtype=torch.float32, device="cuda")
+    plan.xi2(ser[1], pk[1], prev=ser[0], next=ser[2], out=out)
+    torch.cuda.synchronize()
+    plan.profile(True)
+    for _ in range(reps):
+        plan.xi2(ser[1], pk[1], prev=ser[0], next=ser[2], out=out)
+    torch.cuda.synchronize()
+    ms, n = plan.profile_read()["xi2"]
+    plan.profile(False)
+    finite = bool(torch.isfinite(out).all().item())
+    del ser, pk, out
+    nd = w.n_detectors
+    byt = sum(nd * b.n_templates * (8 * A + 20 + 4) + b.n_templates * 8 * A for b, A in zip(w.banks, lengths))
+    return {"ms": ms / max(n, 1), "launches": n, "bytes": byt, "finite": finite,
+            "acf_lengths": {str(a): lengths.count(a) for a in sorted(set(lengths))}}
+
+
 def parity_and_baseline(plan, w, x, strides, k: int, seconds: float):
     """Oracle (FP64, host cores) on detector 0 for stride k of as many banks
     as fit in `seconds`; GPU series of the same banks and stride from a fresh
@@ -186,6 +229,8 @@ def main() -> int:
                                                  "e.g. corr_split=8192,corr_group=32,mix_group=16")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--xi2", type=int, default=-1,
+                    help="also time the xi^2 statistic at the triggers (-1: all workloads but the largest)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -255,6 +300,16 @@ def main() -> int:
     peak = kernel_peak(args.precision, dom)
     kernel_ms = {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items()}
 
+    xi2 = None
+    if args.xi2 == 1 or (args.xi2 == -1 and args.workload != "largest"):
+        m = xi2_measure(plan, w, strides, min(steps, 16))
+        gbs = m["bytes"] / (m["ms"] / 1e3) / 1e9
+        xi2 = {"ms": m["ms"], "launches": m["launches"], "acf_lengths": m["acf_lengths"], "finite": m["finite"],
+               "roofline": {"bound": "hbm", "kernel": "xi2", "achieved": gbs, "peak": HBM_GBS, "unit": "GB/s",
+                            "frac": gbs / HBM_GBS, "bytes_per_launch": m["bytes"],
+                            "traffic": measured_traffic("xi2", args.workload, args.precision)}}
+        log(f"xi2: {m['ms']:.4f} ms per launch, {gbs:.0f} GB/s")
+
     base = err = None
     if not args.no_cpu_baseline:
         base, err, nb = parity_and_baseline(plan, w, x, strides, k_par, args.cpu_seconds)
@@ -287,6 +342,7 @@ def main() -> int:
         "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": measured_traffic(dom, args.workload, args.precision)},
         "kernel_ms": kernel_ms,
+        "xi2": xi2,
         "snr_err": err,
         "compare": compare,
         "cpu_baseline": base,
