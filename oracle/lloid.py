@@ -17,6 +17,8 @@ primitives:
                        recursion of the pre-synchronisation equation
   triggers          -- Sec. II.D.1: max |complex SNR| per template per window
   xi^2              -- Sec. II.D.2: signal-consistency statistic at a trigger
+  coincidence       -- Sec. II.D.3-4: overlapping trigger windows, coincident
+                       events across detectors, one event per sub-bank
 
 Readings of points the paper leaves open are stated where they are used:
 
@@ -59,6 +61,20 @@ Readings of points the paper leaves open are stated where they are used:
   samples outside the available SNR are left out of both sums.
 * R22 xi^2 is evaluated at every per-stride peak (R13), with z(0) the SNR
   at the peak index; the threshold flag is left to the caller.
+* R23 trigger-finding windows extend into the past: window k covers
+  top-rate samples [kF - O, (k+1)F) with O the overlap (light travel time
+  plus the coincidence buffer, in samples); the first window is [0, F).
+  Indices are reported relative to kF (negative inside the overlap).
+* R24 coincidence is per template (the same template in every detector):
+  for every detector a whose trigger reaches the threshold, the candidate
+  event holds a and every other detector d whose trigger reaches the
+  threshold within w[a][d] samples of a's; it is an event if it holds at
+  least two detectors; network SNR = sqrt of the sum of the held SNR^2.
+  The template's event is its candidate with the largest network SNR
+  (lowest anchor detector on ties).
+* R25 clustering keeps, per sub-bank and window, the event with the largest
+  network SNR (lowest template on ties).  Network SNR^2 is summed in
+  detector order in float32, the precision the GPU decides in.
 * normalisation: each real row is scaled so that sum_s sum_l W^s[r,l]^2 = 1
   (the reconstructed template has unit norm), computed in float64.
 """
@@ -519,3 +535,61 @@ def xi2(z: np.ndarray, t_peak: np.ndarray, R: np.ndarray) -> np.ndarray:
     num = np.sum(np.where(have, np.abs(zt - z0 * R) ** 2, 0.0), axis=1)
     den = np.sum(np.where(have, 2.0 - 2.0 * np.abs(R) ** 2, 0.0), axis=1)
     return num / den
+
+
+# ---------------------------------------------------------------------------
+# Overlapping trigger windows, coincidence, clustering (Sec. II.D.3-4)
+# ---------------------------------------------------------------------------
+
+def window_trigger(z_prev: Optional[np.ndarray], z_cur: np.ndarray, overlap: int,
+                   threshold: float = SNR_THRESHOLD) -> Peaks:
+    """Trigger per template over window k = the last `overlap` samples of
+    stride k-1 followed by stride k (reading R23; z_prev None: the first,
+    shortened window).  Index relative to the start of stride k."""
+    if z_prev is None or overlap == 0:
+        return window_peaks(z_cur, threshold)
+    w = np.concatenate([z_prev[:, z_prev.shape[1] - overlap:], z_cur], axis=1)
+    p = window_peaks(w, threshold)
+    return Peaks(p.snr, p.index - overlap, p.value, p.above)
+
+
+@dataclass
+class Event:
+    template: int          # -1: no coincident event in the sub-bank
+    network_snr: float
+    det_mask: int          # detectors held by the event
+
+
+def coincident_events(snr: np.ndarray, index: np.ndarray, above: np.ndarray,
+                      window: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
+    """Per template (columns of the [n_det, M] trigger arrays), the network
+    SNR^2 (float32, summed in detector order) and detector mask of its best
+    coincident event (reading R24); 0 and 0 where there is none."""
+    n_det, M = snr.shape
+    best2 = np.zeros(M, np.float32)
+    best_mask = np.zeros(M, np.int64)
+    for m in range(M):
+        for a in range(n_det):
+            if not above[a, m]:
+                continue
+            held = [d for d in range(n_det)
+                    if above[d, m] and (d == a or abs(int(index[d, m]) - int(index[a, m])) <= window[a, d])]
+            if len(held) < 2:
+                continue
+            s2 = np.float32(0.0)
+            for d in held:
+                s2 = np.float32(s2 + np.float32(snr[d, m]) * np.float32(snr[d, m]))
+            if s2 > best2[m]:
+                best2[m] = s2
+                best_mask[m] = sum(1 << d for d in held)
+    return best2, best_mask
+
+
+def cluster(best2: np.ndarray, mask: np.ndarray) -> Event:
+    """One event per sub-bank and window (reading R25): the largest network
+    SNR, lowest template on ties."""
+    if not np.any(mask):
+        return Event(-1, 0.0, 0)
+    cand = np.where(mask != 0)[0]
+    m = int(cand[np.argmax(best2[cand])])          # argmax takes the first maximum
+    return Event(m, float(np.sqrt(np.float32(best2[m]), dtype=np.float32)), int(mask[m]))
