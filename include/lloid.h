@@ -303,18 +303,58 @@ lloid_status lloid_set_autocorrelation(lloid_plan *plan, const double *acf_dev, 
 lloid_status lloid_xi2(lloid_plan *plan, const float *prev_dev, const float *cur_dev, const float *next_dev,
                        const lloid_peak *peaks_dev, float *xi2_dev, void *stream);
 
+/* Overlapping trigger windows, coincidence and clustering (Sec. II.D.3-4).
+ *
+ * Window k covers top-rate samples [kF - overlap, (k+1)F): its trigger per
+ * template and detector is the maximum |z| over the last `overlap` samples
+ * of stride k - 1 and the whole of stride k (the earlier sample on ties);
+ * the first window (prev_dev NULL) is stride k alone.  Coincidence is per
+ * template: every detector whose window trigger reaches the plan's
+ * threshold anchors a candidate that holds it and each other such detector
+ * whose trigger lies within window[anchor][other] samples (inclusive); a
+ * candidate holding two or more detectors is an event with network SNR
+ * sqrt(sum of the held SNR^2).  A template keeps its best candidate (the
+ * lowest anchor on ties) and each sub-bank keeps its best template (the
+ * lowest on ties): at most one event per bank and window.  Network SNR^2
+ * is summed in detector order in FP32.
+ *   prev_dev     device, series of stride k - 1 as lloid_push_stride writes
+ *                it, or NULL (first window)
+ *   peaks_dev    device, the triggers of stride k (lloid_push_stride)
+ *   overlap      samples, 0 <= overlap <= F: the largest light travel time
+ *                between the detectors plus the coincidence buffer
+ *   window       host [n_det][n_det] int32, samples >= 0: per detector pair
+ *                the light travel time plus the buffer (diagonal unused)
+ *   triggers_dev device, receives the window triggers [LLOID_Q_N_PEAKS]
+ *                (lloid_peak; index relative to the start of stride k,
+ *                negative inside the overlap)
+ *   events_dev   device, receives one lloid_event per bank
+ * Errors: LLOID_E_ARG (NULL peaks, window or outputs), LLOID_E_SHAPE
+ * (overlap outside [0, F], a negative window), LLOID_E_UNSUPPORTED (more
+ * than 8 detectors), LLOID_E_NOMEM, LLOID_E_HIP. */
+typedef struct {
+    float network_snr;        /* 0 when the bank has no event             */
+    int32_t template_index;   /* template within the bank, -1: no event   */
+    uint32_t det_mask;        /* bit d: detector d's trigger is held      */
+    int32_t n_det;            /* detectors held (0: no event)             */
+} lloid_event;
+lloid_status lloid_coincidence(lloid_plan *plan, const float *prev_dev, const lloid_peak *peaks_dev, int32_t overlap,
+                               const int32_t *window, lloid_peak *triggers_dev, lloid_event *events_dev,
+                               void *stream);
+
 /* Per-kernel timing of lloid_push_stride with HIP events recorded on the
  * call's stream around each of the stride's kernels:
  *   0 ingest, 1 decimation, 2 basis correlation, 3 split reduction,
  *   4 mixing + upsample-and-add + series + peak candidates, 5 triggers,
- *   and 6 xi^2 for lloid_xi2.
+ *   6 xi^2 for lloid_xi2, 7 window triggers and 8 coincidence for
+ *   lloid_coincidence.
  * lloid_profile_enable(plan, 1) starts a new accumulation (0 stops it);
  * lloid_profile_read synchronises the recorded events and returns the
  * summed duration (ms) and the number of launches of one kernel since the
  * accumulation started.  Errors: LLOID_E_ARG, LLOID_E_HIP. */
 typedef enum {
     LLOID_K_INGEST = 0, LLOID_K_DOWN = 1, LLOID_K_CORR = 2,
-    LLOID_K_REDUCE = 3, LLOID_K_MIX = 4, LLOID_K_PEAKS = 5, LLOID_K_XI2 = 6, LLOID_K_COUNT = 7
+    LLOID_K_REDUCE = 3, LLOID_K_MIX = 4, LLOID_K_PEAKS = 5, LLOID_K_XI2 = 6,
+    LLOID_K_TRIGGERS = 7, LLOID_K_COINC = 8, LLOID_K_COUNT = 9
 } lloid_kernel_id;
 lloid_status lloid_profile_enable(lloid_plan *plan, int32_t enable);
 lloid_status lloid_profile_read(lloid_plan *plan, int32_t kernel, double *total_ms, int64_t *launches);

@@ -22,7 +22,7 @@ Q_N_SLICES, Q_SLICE_LOOKAHEAD, Q_FLOPS_PER_STRIDE, Q_DEVICE_BYTES = 8, 9, 10, 11
 Q_OPTION = 12
 OPTIONS = {"graph": 0, "corr_split": 1, "corr_group": 2, "mix_group": 3, "corr_cols": 4}
 INSPECT_DOWNSAMPLED, INSPECT_BASIS_OUT = 0, 1
-KERNEL_NAMES = ["ingest", "down", "corr", "reduce", "mix", "peaks", "xi2"]
+KERNEL_NAMES = ["ingest", "down", "corr", "reduce", "mix", "peaks", "xi2", "triggers", "coinc"]
 
 
 class LloidError(RuntimeError):
@@ -90,6 +90,8 @@ def load() -> ctypes.CDLL:
     lib.lloid_set_autocorrelation.restype = ctypes.c_int
     lib.lloid_xi2.argtypes = [P, P, P, P, P, P, P]
     lib.lloid_xi2.restype = ctypes.c_int
+    lib.lloid_coincidence.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P, P, P]
+    lib.lloid_coincidence.restype = ctypes.c_int
     lib.lloid_set_option.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
     lib.lloid_set_option.restype = ctypes.c_int
     lib.lloid_status_string.argtypes = [ctypes.c_int]

@@ -17,6 +17,7 @@
 #include <new>
 #include <vector>
 
+#include "lloid_coinc.h"
 #include "lloid_internal.h"
 #include "lloid_xi2.h"
 
@@ -115,6 +116,10 @@ struct lloid_plan {
     float *d_acf = nullptr;
     int32_t n_xi = 0;
     size_t xi_bytes = 0;
+
+    // coincidence: per-template and per-bank tables (built on first use)
+    TrigTemplate *d_trigtab = nullptr;
+    CoincBank *d_coincbanks = nullptr;
 
     // graph mode (LLOID_OPT_GRAPH)
     bool use_graph = false;
@@ -1295,6 +1300,54 @@ lloid_status lloid_xi2(lloid_plan *P, const float *prev, const float *cur, const
     HIP_OK(P->mark(LLOID_K_XI2, st, true));
     HIP_OK(launch_xi2(st, P->d_xitab, P->n_xi, P->n_det, P->F, prev, cur, next, peaks, P->d_acf, out));
     HIP_OK(P->mark(LLOID_K_XI2, st, false));
+    return LLOID_OK;
+}
+
+lloid_status lloid_coincidence(lloid_plan *P, const float *prev, const lloid_peak *peaks, int32_t overlap,
+                               const int32_t *window, lloid_peak *triggers, lloid_event *events, void *stream) {
+    if (!P || !peaks || !window || !triggers || !events) return LLOID_E_ARG;
+    if (P->n_det > kCoincMaxDet) return LLOID_E_UNSUPPORTED;
+    if (overlap < 0 || overlap > P->F) return LLOID_E_SHAPE;
+    CoincWindows w{};
+    for (int a = 0; a < P->n_det; ++a)
+        for (int d = 0; d < P->n_det; ++d) {
+            if (window[a * P->n_det + d] < 0) return LLOID_E_SHAPE;
+            w.w[a][d] = window[a * P->n_det + d];
+        }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!P->d_trigtab) {
+        std::vector<TrigTemplate> tab;
+        std::vector<CoincBank> cb;
+        tab.reserve((size_t)P->total_templates);
+        for (const PBank &pb : P->banks) {
+            for (int m = 0; m < pb.M; ++m) {
+                TrigTemplate e{};
+                e.series_off = pb.series_off + (int64_t)m * P->F * 2;
+                e.det_stride = (int64_t)pb.M * P->F * 2;
+                e.peak_off = pb.peak_off + m;
+                e.M = pb.M;
+                tab.push_back(e);
+            }
+            CoincBank c{};
+            c.peak_off = pb.peak_off;
+            c.M = pb.M;
+            cb.push_back(c);
+        }
+        TrigTemplate *t = nullptr;
+        CoincBank *c = nullptr;
+        ST_OK(upload(P, &t, tab, st));
+        ST_OK(upload(P, &c, cb, st));
+        HIP_OK(hipStreamSynchronize(st));
+        P->d_trigtab = t;
+        P->d_coincbanks = c;
+    }
+    HIP_OK(P->mark(LLOID_K_TRIGGERS, st, true));
+    HIP_OK(launch_window_triggers(st, P->d_trigtab, (int32_t)P->total_templates, P->n_det, P->F, prev, peaks, overlap,
+                                  P->cfg.snr_threshold, triggers));
+    HIP_OK(P->mark(LLOID_K_TRIGGERS, st, false));
+    HIP_OK(P->mark(LLOID_K_COINC, st, true));
+    HIP_OK(launch_coinc(st, P->d_coincbanks, (int32_t)P->banks.size(), P->n_det, w, triggers, events));
+    HIP_OK(P->mark(LLOID_K_COINC, st, false));
     return LLOID_OK;
 }
 

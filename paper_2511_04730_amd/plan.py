@@ -183,6 +183,33 @@ class LloidPlan:
         off = self.bank_peak_offset[bank]
         return xi2[off:off + self.n_detectors * M].cpu().numpy().reshape(self.n_detectors, M)
 
+    # ------------------------------------------------------------ coincidence
+    def coincidence(self, peaks, window, overlap: int, prev=None, triggers=None, events=None, stream=None):
+        """Window triggers (last `overlap` samples of the previous stride's
+        series `prev` plus this stride's `peaks`), coincident events and one
+        event per bank.  window: [n_det][n_det] samples.  Returns (triggers,
+        events): device tensors in the peaks layout and [n_banks, 4] int32
+        (network SNR bits, template, detector mask, detectors held)."""
+        import torch
+        nd = self.n_detectors
+        w = np.ascontiguousarray(np.asarray(window, dtype=np.int32).reshape(nd, nd))
+        if triggers is None:
+            triggers = self.new_peaks()
+        if events is None:
+            events = torch.empty(self.n_banks * 4, dtype=torch.int32, device="cuda")
+        ptr = (lambda t: ctypes.c_void_p(t.data_ptr()) if t is not None else None)
+        L.check(self.lib.lloid_coincidence(self.handle, ptr(prev), ptr(peaks), int(overlap),
+                                           w.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ptr(triggers),
+                                           ptr(events), _stream_handle(stream)), "lloid_coincidence")
+        return triggers, events
+
+    def events_view(self, events) -> list:
+        """Per bank (template, network SNR, detector mask, detectors held);
+        template -1 when the bank has no event."""
+        raw = events.view(-1, 4).cpu().numpy()
+        snr = raw[:, 0].copy().view(np.float32)
+        return [(int(r[1]), float(s), int(np.uint32(r[2])), int(r[3])) for r, s in zip(raw, snr)]
+
     # ------------------------------------------------------------ gradient
     def slice_shapes(self):
         """(2M, L, N) of every slice, banks in order."""
