@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 METRIC = "template SNR-samples/sec per MI355X, batched BF16 vs plain FP32 at SNR err≤1e-3"
 PEAK_TFLOPS = {"fp32": 157.3, "bf16x3": 2500.0, "fp16": 2500.0, "fp8_bf16": 5000.0}
 HBM_GBS = 8000.0   # MI355X HBM3E peak
+COINC_OVERLAP_S = 0.0273 + 0.005   # H-L-V light travel time + coincidence buffer
 
 
 def kernel_peak(precision: str, kernel: str) -> float:
@@ -66,7 +67,8 @@ def workload(name: str):
 
 KERNEL_SOURCES = {"mix": ["lloid_mix.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
                   "corr": ["lloid_corr.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
-                  "xi2": ["lloid_xi2.hip", "lloid_xi2.h", "lloid_internal.h", "lloid_device.h"]}
+                  "xi2": ["lloid_xi2.hip", "lloid_xi2.h", "lloid_internal.h", "lloid_device.h"],
+                  "window_trigger": ["lloid_coinc.hip", "lloid_coinc.h", "lloid_internal.h", "lloid_device.h"]}
 
 
 def source_digest(kernel: str) -> str:
@@ -138,13 +140,16 @@ def timed(plan, strides, warmup: int, steps: int, write: bool, profile: bool):
     return ms, prof
 
 
-def xi2_measure(plan, w, strides, reps: int):
-    """xi^2 (Sec. II.D.2) at the triggers of stride 1, from the series of
-    strides 0..2 of every bank and detector, with seeded chirp-like
-    autocorrelations of 351 or 701 samples per bank.  Returns a dict with
-    the mean duration of one launch (HIP events over `reps` launches) and
-    its algorithmic HBM bytes: per trigger the A-sample complex window, the
-    trigger entry and the output; per template its autocorrelation."""
+def downstream_measure(plan, w, strides, reps: int):
+    """The consumers of the SNR series on strides 0..2 of every bank and
+    detector, each timed over `reps` launches with HIP events:
+    xi^2 (Sec. II.D.2) at the triggers of stride 1 with seeded chirp-like
+    autocorrelations of 351 or 701 samples per bank (algorithmic bytes: per
+    trigger the A-sample complex window, the trigger and the output; per
+    template its autocorrelation), and the overlapping trigger windows plus
+    coincidence and clustering (Sec. II.D.3-4) of stride 2 with the H-L-V
+    overlap of 0.0323 s (window triggers: per trigger the overlap's complex
+    samples, the stride trigger read and the window trigger written)."""
     import numpy as np
     import torch
     import synth
@@ -163,20 +168,31 @@ def xi2_measure(plan, w, strides, reps: int):
     for k in range(3):
         plan.push(strides[k], series=ser[k], peaks=pk[k])
     out = torch.empty(plan.n_peaks, dtype=torch.float32, device="cuda")
+    nd = w.n_detectors
+    ov = int(round(COINC_OVERLAP_S * w.sample_rate))
+    win = np.full((nd, nd), ov)
+    trig, ev = plan.coincidence(pk[2], win, ov, prev=ser[1])
     plan.xi2(ser[1], pk[1], prev=ser[0], next=ser[2], out=out)
     torch.cuda.synchronize()
     plan.profile(True)
     for _ in range(reps):
         plan.xi2(ser[1], pk[1], prev=ser[0], next=ser[2], out=out)
+    for _ in range(reps):
+        plan.coincidence(pk[2], win, ov, prev=ser[1], triggers=trig, events=ev)
     torch.cuda.synchronize()
-    ms, n = plan.profile_read()["xi2"]
+    prof = plan.profile_read()
     plan.profile(False)
+    ms, n = prof["xi2"]
     finite = bool(torch.isfinite(out).all().item())
-    del ser, pk, out
-    nd = w.n_detectors
+    n_events = sum(1 for e in plan.events_view(ev) if e[0] >= 0)
+    del ser, pk, out, trig, ev
     byt = sum(nd * b.n_templates * (8 * A + 20 + 4) + b.n_templates * 8 * A for b, A in zip(w.banks, lengths))
+    n_trig = nd * w.n_templates
     return {"ms": ms / max(n, 1), "launches": n, "bytes": byt, "finite": finite,
-            "acf_lengths": {str(a): lengths.count(a) for a in sorted(set(lengths))}}
+            "acf_lengths": {str(a): lengths.count(a) for a in sorted(set(lengths))},
+            "trig_ms": prof["triggers"][0] / max(prof["triggers"][1], 1),
+            "coinc_ms": prof["coinc"][0] / max(prof["coinc"][1], 1),
+            "trig_bytes": n_trig * (8 * ov + 20 + 20), "events": n_events, "overlap": ov}
 
 
 def parity_and_baseline(plan, w, x, strides, k: int, seconds: float):
@@ -230,7 +246,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--xi2", type=int, default=-1,
-                    help="also time the xi^2 statistic at the triggers (-1: all workloads but the largest)")
+                    help="also time xi^2 and coincidence on the triggers (-1: all workloads but the largest)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -300,15 +316,22 @@ def main() -> int:
     peak = kernel_peak(args.precision, dom)
     kernel_ms = {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items()}
 
-    xi2 = None
+    xi2 = coinc = None
     if args.xi2 == 1 or (args.xi2 == -1 and args.workload != "largest"):
-        m = xi2_measure(plan, w, strides, min(steps, 16))
+        m = downstream_measure(plan, w, strides, min(steps, 16))
         gbs = m["bytes"] / (m["ms"] / 1e3) / 1e9
         xi2 = {"ms": m["ms"], "launches": m["launches"], "acf_lengths": m["acf_lengths"], "finite": m["finite"],
                "roofline": {"bound": "hbm", "kernel": "xi2", "achieved": gbs, "peak": HBM_GBS, "unit": "GB/s",
                             "frac": gbs / HBM_GBS, "bytes_per_launch": m["bytes"],
                             "traffic": measured_traffic("xi2", args.workload, args.precision)}}
-        log(f"xi2: {m['ms']:.4f} ms per launch, {gbs:.0f} GB/s")
+        tgbs = m["trig_bytes"] / (m["trig_ms"] / 1e3) / 1e9
+        coinc = {"overlap_samples": m["overlap"], "window_ms": m["trig_ms"], "coinc_ms": m["coinc_ms"],
+                 "banks_with_event": m["events"],
+                 "roofline": {"bound": "hbm", "kernel": "window_trigger", "achieved": tgbs, "peak": HBM_GBS,
+                              "unit": "GB/s", "frac": tgbs / HBM_GBS, "bytes_per_launch": m["trig_bytes"],
+                              "traffic": measured_traffic("window_trigger", args.workload, args.precision)}}
+        log(f"xi2: {m['ms']:.4f} ms per launch, {gbs:.0f} GB/s; window triggers {m['trig_ms']:.4f} ms, "
+            f"coincidence {m['coinc_ms']:.4f} ms, {m['events']} banks with an event")
 
     base = err = None
     if not args.no_cpu_baseline:
@@ -343,6 +366,7 @@ def main() -> int:
                      "frac": achieved / peak, "traffic": measured_traffic(dom, args.workload, args.precision)},
         "kernel_ms": kernel_ms,
         "xi2": xi2,
+        "coincidence": coinc,
         "snr_err": err,
         "compare": compare,
         "cpu_baseline": base,

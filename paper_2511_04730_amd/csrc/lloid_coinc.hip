@@ -4,8 +4,9 @@
 // Window k covers top-rate samples [kF - O, (k+1)F): the stride's trigger
 // (from the peak kernel) merged with the maximum of |z| over the last O
 // samples of the previous stride's series, the earlier sample winning ties.
-// One wave per template scans those O contiguous complex samples of every
-// detector (template-major series: 512 contiguous bytes per load).
+// One wave per template scans those O contiguous complex samples of up to
+// four detectors at once (template-major series: 512 contiguous bytes per
+// load).
 //
 // Coincidence is per template: each detector whose window trigger reaches
 // the threshold anchors a candidate holding every other such detector
@@ -27,6 +28,8 @@ namespace lloid {
 namespace {
 
 constexpr int kTrigWaves = 4;    // templates per work group
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 constexpr int kCoincThreads = 256;
 
 __device__ __forceinline__ void max_first(float &p2, int &idx, float &re, float &im, int o) {
@@ -42,45 +45,83 @@ __device__ __forceinline__ void max_first(float &p2, int &idx, float &re, float 
     }
 }
 
+// Detectors d0 .. d0 + ND - 1 of every template: the overlap loads of all
+// of them for four 64-sample chunks are issued before the first is used
+// (lanes past the overlap re-read its last sample and are masked out of the
+// maximum; the running maximum is updated with selects, not branches, so
+// no branch holds a load's wait inside its iteration).
+template <int ND>
 __global__ __launch_bounds__(64 * kTrigWaves) void window_trigger_kernel(
-    const TrigTemplate *__restrict__ tab, int32_t n_tmpl, int32_t n_det, int32_t F, const float *__restrict__ prev,
+    const TrigTemplate *__restrict__ tab, int32_t n_tmpl, int32_t d0, int32_t F, const float *__restrict__ prev,
     const lloid_peak *__restrict__ peaks, int32_t overlap, float threshold, lloid_peak *__restrict__ triggers) {
     const int lane = threadIdx.x & 63;
     const int i = __builtin_amdgcn_readfirstlane(blockIdx.x * kTrigWaves + (threadIdx.x >> 6));
     if (i >= n_tmpl) return;
     const TrigTemplate e = tab[i];
-    for (int det = 0; det < n_det; ++det) {
-        const int64_t pk = e.peak_off + (int64_t)det * e.M;
-        const lloid_peak cur = peaks[pk];
-        if (!prev || overlap == 0) {              // first (shortened) window: the stride itself
-            if (lane == 0) triggers[pk] = cur;
-            continue;
+    if (!prev || overlap == 0) {                  // first (shortened) window: the stride itself
+        if (lane < ND) {
+            const int64_t pk = e.peak_off + (int64_t)(d0 + lane) * e.M;
+            triggers[pk] = peaks[pk];
         }
-        // the overlap's samples: index -overlap .. -1 relative to the stride
-        const float *z = prev + e.series_off + (int64_t)det * e.det_stride;
-        float p2 = -1.f, re = 0.f, im = 0.f;
-        int idx = 0x7fffffff;
-        for (int c = lane; c < overlap; c += 64) {
-            const int t = F - overlap + c;
-            const float2 v = *reinterpret_cast<const float2 *>(z + 2 * (int64_t)t);
-            const float q2 = v.x * v.x + v.y * v.y;
-            if (better(q2, c - overlap, p2, idx)) {
-                p2 = q2;
-                idx = c - overlap;
-                re = v.x;
-                im = v.y;
+        return;
+    }
+    // lane j < ND reads detector j's stride trigger now, so that its load
+    // overlaps the overlap's loads
+    const int64_t pk = e.peak_off + (int64_t)(d0 + (lane < ND ? lane : 0)) * e.M;
+    const lloid_peak cur = peaks[pk];
+    float p2[ND], re[ND], im[ND];
+    int idx[ND];
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        p2[j] = -1.f;
+        re[j] = im[j] = 0.f;
+        idx[j] = 0x7fffffff;
+    }
+    // the overlap's samples: index -overlap .. -1 relative to the stride
+    // groups of four 64-sample chunks, every load in flight at once (chunks
+    // past the overlap re-read its last sample, masked)
+    for (int c0 = 0; c0 < overlap; c0 += 4 * 64) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = c0 + u * 64 + lane;
+            const bool in = k < overlap;
+            const int t = F - overlap + (in ? k : overlap - 1);
+#pragma unroll
+            for (int j = 0; j < ND; ++j) {
+                const float *z = prev + e.series_off + (int64_t)(d0 + j) * e.det_stride;
+                const f32x2 v = ld_global<f32x2>(z + 2 * (int64_t)t);
+                const float q2 = in ? v.x * v.x + v.y * v.y : -2.f;   // below the initial -1: never taken
+                const bool take = (q2 > p2[j]) | ((q2 == p2[j]) & (k - overlap < idx[j]));
+                p2[j] = take ? q2 : p2[j];
+                idx[j] = take ? k - overlap : idx[j];
+                re[j] = take ? v.x : re[j];
+                im[j] = take ? v.y : im[j];
             }
         }
-        for (int o = 32; o >= 1; o >>= 1) max_first(p2, idx, re, im, o);
-        if (lane == 0) {
-            const float c2 = cur.re * cur.re + cur.im * cur.im;
-            // the overlap precedes the stride: it wins ties
-            if (p2 >= c2) {
-                const float snr = sqrtf(p2);
-                triggers[pk] = lloid_peak{snr, idx, re, im, snr >= threshold ? 1 : 0};
-            } else {
-                triggers[pk] = cur;
+    }
+#pragma unroll
+    for (int j = 0; j < ND; ++j) {
+        for (int o = 32; o >= 1; o >>= 1) max_first(p2[j], idx[j], re[j], im[j], o);
+    }
+    if (lane < ND) {
+        // lane j finishes detector j (the values are wave-uniform after the reduction)
+        float bp2 = p2[0], bre = re[0], bim = im[0];
+        int bidx = idx[0];
+#pragma unroll
+        for (int j = 1; j < ND; ++j) {
+            if (lane == j) {
+                bp2 = p2[j];
+                bre = re[j];
+                bim = im[j];
+                bidx = idx[j];
             }
+        }
+        const float c2 = cur.re * cur.re + cur.im * cur.im;
+        if (bp2 >= c2) {                          // the overlap precedes the stride: it wins ties
+            const float snr = sqrtf(bp2);
+            triggers[pk] = lloid_peak{snr, bidx, bre, bim, snr >= threshold ? 1 : 0};
+        } else {
+            triggers[pk] = cur;
         }
     }
 }
@@ -189,10 +230,18 @@ hipError_t launch_window_triggers(hipStream_t st, const TrigTemplate *tab, int32
                                   const float *prev, const lloid_peak *peaks, int32_t overlap, float threshold,
                                   lloid_peak *triggers) {
     if (n_tmpl <= 0) return hipSuccess;
-    const int blocks = (n_tmpl + kTrigWaves - 1) / kTrigWaves;
-    hipLaunchKernelGGL(window_trigger_kernel, dim3(blocks), dim3(64 * kTrigWaves), 0, st, tab, n_tmpl, n_det, F, prev,
-                       peaks, overlap, threshold, triggers);
-    return hipGetLastError();
+    const dim3 grid((n_tmpl + kTrigWaves - 1) / kTrigWaves), block(64 * kTrigWaves);
+    for (int d0 = 0; d0 < n_det; d0 += 4) {
+        switch (n_det - d0 < 4 ? n_det - d0 : 4) {
+            case 1: hipLaunchKernelGGL(window_trigger_kernel<1>, grid, block, 0, st, tab, n_tmpl, d0, F, prev, peaks, overlap, threshold, triggers); break;
+            case 2: hipLaunchKernelGGL(window_trigger_kernel<2>, grid, block, 0, st, tab, n_tmpl, d0, F, prev, peaks, overlap, threshold, triggers); break;
+            case 3: hipLaunchKernelGGL(window_trigger_kernel<3>, grid, block, 0, st, tab, n_tmpl, d0, F, prev, peaks, overlap, threshold, triggers); break;
+            default: hipLaunchKernelGGL(window_trigger_kernel<4>, grid, block, 0, st, tab, n_tmpl, d0, F, prev, peaks, overlap, threshold, triggers); break;
+        }
+        const hipError_t err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_coinc(hipStream_t st, const CoincBank *banks, int32_t n_banks, int32_t n_det, const CoincWindows &w,
