@@ -314,7 +314,7 @@ def main() -> int:
     avg_ms = prof[dom][0] / max(prof[dom][1], 1)
     achieved = kf[dom] / (avg_ms / 1e3) / 1e12
     peak = kernel_peak(args.precision, dom)
-    kernel_ms = {k: round(v[0] / max(v[1], 1), 5) for k, v in prof.items()}
+    kernel_ms = {k: round(v[0] / v[1], 5) for k, v in prof.items() if v[1] > 0}   # the stride's kernels
 
     xi2 = coinc = None
     if args.xi2 == 1 or (args.xi2 == -1 and args.workload != "largest"):
