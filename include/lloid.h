@@ -293,9 +293,13 @@ lloid_status lloid_set_option(lloid_plan *plan, int32_t option, int64_t value);
  *             next may be NULL (first or last stride of the data): samples
  *             there are left out of both sums.  With next_dev given, call
  *             after stride k + 1 has been filtered (delta samples of latency).
- *   peaks_dev device, the triggers of stride k (lloid_push_stride)
+ *   peaks_dev device, the triggers of stride k: those of lloid_push_stride
+ *             (index in [0, F)) or the window triggers of lloid_coincidence
+ *             (index in [-F, F), negative inside the previous stride, which
+ *             prev_dev must then hold)
  *   xi2_dev   device float32 [LLOID_Q_N_PEAKS], entry for entry with the
- *             triggers; NaN where a trigger index lies outside the stride.
+ *             triggers; NaN where a trigger index lies outside [0, F), or
+ *             outside [-F, F) when prev_dev is given.
  * Errors: LLOID_E_ARG (NULL cur, peaks or output), LLOID_E_STATE (no
  * autocorrelations stored), LLOID_E_HIP. */
 lloid_status lloid_set_autocorrelation(lloid_plan *plan, const double *acf_dev, const int32_t *acf_len,

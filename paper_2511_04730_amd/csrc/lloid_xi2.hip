@@ -68,10 +68,12 @@ __global__ __launch_bounds__(64 * kXiWaves) void xi2_kernel(const XiTemplate *__
     for (int j = 0; j < ND; ++j) {
         const int64_t row = e.series_off + (int64_t)(d0 + j) * e.det_stride;   // float offset of z[0]
         const int t = __builtin_amdgcn_readfirstlane(peaks[e.peak_off + (int64_t)(d0 + j) * e.M].index);
-        ok[j] = t >= 0 && t < F;              // else: not a trigger of this stride
+        // a trigger of this stride, or of its window's overlap into the previous one
+        ok[j] = (t >= 0 && t < F) || (hp && t >= -F && t < 0);
         tp[j] = ok[j] ? t : 0;
         zrow[j] = reinterpret_cast<const char *>(cur + row);
-        z0[j] = ld_global<f32x2>(cur + row + 2 * (int64_t)tp[j]);
+        z0[j] = tp[j] < 0 ? ld_global<f32x2>(prev + row + 2 * (int64_t)(tp[j] + F))
+                          : ld_global<f32x2>(cur + row + 2 * (int64_t)tp[j]);
         num[j] = den[j] = 0.f;
     }
     // a uniform trip count (lanes past the window re-read its last sample and
@@ -85,14 +87,15 @@ __global__ __launch_bounds__(64 * kXiWaves) void xi2_kernel(const XiTemplate *__
         const float w = 2.f - 2.f * (r.x * r.x + r.y * r.y);
 #pragma unroll
         for (int j = 0; j < ND; ++j) {
-            const int s = tp[j] - delta + t;  // in [-F, 2F) since delta <= F
+            const int s = tp[j] - delta + t;  // in [-2F, 2F) since delta <= F and tp >= -F
+            const bool lo2 = s < -F;          // before the previous stride: never available
             const bool lo = s < 0, hi = s >= F;
-            const int sl = lo ? s + F : (hi ? s - F : s);
+            const int sl = lo2 ? 0 : (lo ? s + F : (hi ? s - F : s));
             const int64_t off = (int64_t)sl * 8 + (lo ? dprev : (hi ? dnext : 0));
             const f32x2 z = ld_global<f32x2>(zrow[j] + off);
             // 1 or 0 as a factor, not a select: a select would let the
             // compiler move the load under a branch (one wait per sample)
-            const float use = (in && (!lo || hp) && (!hi || hn)) ? 1.f : 0.f;
+            const float use = (in && !lo2 && (!lo || hp) && (!hi || hn)) ? 1.f : 0.f;
             const float dre = z.x - (z0[j].x * r.x - z0[j].y * r.y);
             const float dim = z.y - (z0[j].x * r.y + z0[j].y * r.x);
             num[j] += use * (dre * dre + dim * dim);

@@ -209,3 +209,36 @@ def test_errors(plan_cls):
         with pytest.raises(LloidError) as e:
             plan.set_autocorrelation(_acf_tensor(acfs), bad)
         assert e.value.status == -2      # LLOID_E_SHAPE
+
+
+@pytest.mark.parametrize("have_next", [True, False])
+def test_window_trigger_indices_in_the_previous_stride(plan_cls, have_next):
+    """Triggers of an overlapping window (index in [-F, F)): windows reaching
+    before the previous stride drop those samples from both sums."""
+    banks = _ragged_banks()
+    plan = plan_cls(banks, F, 2, "fp32")
+    lengths = [351, 701, 2 * F + 1]
+    acfs = [synth.synthetic_acf(99, b, plan.bank_templates[b], A) for b, A in enumerate(lengths)]
+    plan.set_autocorrelation(_acf_tensor(acfs), lengths)
+    series = _synthetic_series(plan, 7, 3)
+    g = synth.rng_for(97, synth.PURPOSE_STRUCT, 30)
+    raw = np.zeros((plan.n_peaks, 5), np.int32)
+    raw[:, 1] = g.integers(-F, F, plan.n_peaks)
+    for b in range(plan.n_banks):
+        d = (lengths[b] - 1) // 2
+        special = [-F, -1, -132, -d, d - F - 1, d - F, 0, F - 1]
+        off = plan.bank_peak_offset[b]
+        raw[off:off + len(special), 1] = special
+    peaks = torch.from_numpy(raw.reshape(-1)).cuda()
+    got = plan.xi2(series[1], peaks, prev=series[0], next=series[2] if have_next else None)
+    torch.cuda.synchronize()
+    for b in range(plan.n_banks):
+        ref, bound = _oracle_xi2(plan, b, series, raw[:, 1], acfs[b], True, have_next)
+        _check_bank(plan, b, got, ref, bound)
+    # out of range: before the previous stride, or negative without it
+    raw2 = raw.copy()
+    raw2[0, 1] = -F - 1
+    out = plan.xi2(series[1], torch.from_numpy(raw2.reshape(-1)).cuda(), prev=series[0]).cpu().numpy()
+    assert np.isnan(out[0]) and np.all(np.isfinite(out[1:]))
+    out = plan.xi2(series[1], peaks).cpu().numpy()
+    assert np.all(np.isnan(out[raw[:, 1] < 0])) and np.all(np.isfinite(out[raw[:, 1] >= 0]))
