@@ -19,6 +19,8 @@ primitives:
   xi^2              -- Sec. II.D.2: signal-consistency statistic at a trigger
   coincidence       -- Sec. II.D.3-4: overlapping trigger windows, coincident
                        events across detectors, one event per sub-bank
+  whitening         -- Sec. II.B.2: PSD estimation and whitening with
+                       frequency-domain downsampling
 
 Readings of points the paper leaves open are stated where they are used:
 
@@ -75,6 +77,26 @@ Readings of points the paper leaves open are stated where they are used:
 * R25 clustering keeps, per sub-bank and window, the event with the largest
   network SNR (lowest template on ties).  Network SNR^2 is summed in
   detector order in float32, the precision the GPU decides in.
+* R26 whitening blocks: N input samples (a power of two), zero padding Z on
+  each side, hop H = N/2 - Z; the segment of the last 2H inputs times the
+  periodic Hann window sin^2(pi m / 2H), which sums to one at hop H.
+  Frequency-domain downsampling by D keeps the first N/(2D) + 1 bins and
+  inverts with an N/D-point transform (NumPy's irfft: the imaginary parts
+  of the DC and new Nyquist bins are dropped).
+* R27 instantaneous PSD per bin: |X_k|^2 / sum(hann^2) (the variance per
+  sample for white noise).  The running estimate takes the median of the
+  most recent c estimates, c = the largest odd count <= min(blocks seen,
+  n_med), divides it by beta_c = exp(E[log median of c unit exponentials]
+  + gamma) (median to geometric mean of chi^2_2 bins), and updates the log
+  geometric mean by a running average over min(blocks seen, n_avg) blocks;
+  PSD = geometric mean x e^gamma.  The current block's estimate is
+  included before it is whitened.
+* R28 whitened block: Y_k = X_k / sqrt(D PSD_k) (unit variance for white
+  noise), inverse transform, times a Tukey window that is one over the
+  segment and a raised cosine over each Z/D-sample pad, overlap-added;
+  each push outputs the first H/D samples of the accumulator (input times
+  [iH - 2H - Z, iH - H - Z) for push i = 1, 2, ...: latency N/2).  A gap
+  push adds no block and updates no PSD; the accumulator still drains.
 * normalisation: each real row is scaled so that sum_s sum_l W^s[r,l]^2 = 1
   (the reconstructed template has unit norm), computed in float64.
 """
@@ -593,3 +615,77 @@ def cluster(best2: np.ndarray, mask: np.ndarray) -> Event:
     cand = np.where(mask != 0)[0]
     m = int(cand[np.argmax(best2[cand])])          # argmax takes the first maximum
     return Event(m, float(np.sqrt(np.float32(best2[m]), dtype=np.float32)), int(mask[m]))
+
+
+# ---------------------------------------------------------------------------
+# PSD estimation and whitening with frequency-domain downsampling (Sec. II.B.2)
+# ---------------------------------------------------------------------------
+
+def median_bias(c: int) -> float:
+    """beta_c = exp(E[log median of c iid unit exponentials] + gamma) for odd
+    c (reading R27): the median of c chi^2_2 bins over their geometric mean.
+    The median is the order statistic k = (c+1)/2 of c exponentials; its
+    density is integrated numerically (SciPy's quad)."""
+    from scipy import integrate
+    from scipy.special import comb
+    assert c % 2 == 1
+    k = (c + 1) // 2
+    dens = lambda x: comb(c, k) * k * (-np.expm1(-x)) ** (k - 1) * np.exp(-x * (c - k + 1))
+    e_log = integrate.quad(lambda x: np.log(x) * dens(x), 0, np.inf, limit=400, epsabs=1e-13, epsrel=1e-13)[0]
+    return float(np.exp(e_log + np.euler_gamma))
+
+
+class Whitener:
+    """Streaming PSD estimation and whitening of one detector (Sec. II.B.2,
+    readings R26-R28), float64.  push() takes H = N/2 - Z new input samples
+    and returns H / D whitened output samples."""
+
+    def __init__(self, n: int, z: int, d: int = 1, n_med: int = 7, n_avg: int = 64):
+        assert n & (n - 1) == 0 and 0 <= z < n // 4 and n % d == 0 and z % d == 0 and n_med % 2 == 1
+        self.n, self.z, self.d, self.n_med, self.n_avg = n, z, d, n_med, n_avg
+        self.h = n // 2 - z
+        assert self.h % d == 0
+        self.n_out, self.h_out, self.z_out = n // d, self.h // d, z // d
+        self.k_out = self.n_out // 2 + 1
+        m = np.arange(2 * self.h)
+        self.hann = np.sin(np.pi * m / (2 * self.h)) ** 2
+        self.w2 = float(np.sum(self.hann ** 2))
+        tk = np.ones(self.n_out)
+        if self.z_out > 0:
+            r = 0.5 * (1.0 - np.cos(np.pi * np.arange(self.z_out) / self.z_out))
+            tk[:self.z_out] = r
+            tk[self.n_out - self.z_out:] = r[::-1]
+        self.tukey = tk
+        self.beta = {c: median_bias(c) for c in range(1, n_med + 1, 2)}
+        self.seg = np.zeros(2 * self.h)
+        self.acc = np.zeros(self.n_out)
+        self.recent: List[np.ndarray] = []
+        self.log_geo = np.zeros(self.k_out)
+        self.blocks = 0
+
+    @property
+    def psd(self) -> np.ndarray:
+        return np.exp(self.log_geo) * np.exp(np.euler_gamma)
+
+    def push(self, x: np.ndarray, gap: bool = False) -> np.ndarray:
+        x = np.asarray(x, np.float64)
+        assert x.shape == (self.h,)
+        self.seg = np.concatenate([self.seg[self.h:], np.zeros(self.h) if gap else x])
+        if not gap:
+            blk = np.zeros(self.n)
+            blk[self.z:self.z + 2 * self.h] = self.hann * self.seg
+            X = np.fft.rfft(blk)[:self.k_out]                       # frequency-domain downsampling
+            P = (X.real ** 2 + X.imag ** 2) / self.w2                # instantaneous PSD
+            self.recent = (self.recent + [P])[-self.n_med:]
+            self.blocks += 1
+            c = min(self.blocks, self.n_med)
+            c -= 1 - c % 2                                           # largest odd count
+            med = np.median(np.stack(self.recent[-c:]), axis=0)
+            obs = np.log(med / self.beta[c])
+            self.log_geo += (obs - self.log_geo) / min(self.blocks, self.n_avg)
+            Y = X / np.sqrt(self.d * self.psd)
+            y = np.fft.irfft(Y, self.n_out)
+            self.acc += self.tukey * y
+        out = self.acc[:self.h_out].copy()
+        self.acc = np.concatenate([self.acc[self.h_out:], np.zeros(self.h_out)])
+        return out
