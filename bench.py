@@ -195,6 +195,50 @@ def downstream_measure(plan, w, strides, reps: int):
             "trig_bytes": n_trig * (8 * ov + 20 + 20), "events": n_events, "overlap": ov}
 
 
+WHITEN_RATE_IN = 16384   # strain rate the whitener reads (Hz)
+
+
+def whiten_measure(w, reps: int):
+    """Whitening with frequency-domain downsampling (Sec. II.B.2) at the
+    paper's low-latency setting: 4 s blocks of 16384 Hz strain with 1 s of
+    zero padding (one push per second), output at the workload's top rate,
+    median of 7, for every detector.  Returns the mean HIP-event time of one
+    push over `reps` pushes after 8 untimed ones, and its algorithmic bytes
+    per detector: the Hann block (inputs read, complex block written), the
+    Stockham passes of both transforms (each reads and writes every complex
+    value), the PSD update (bins, median ring, log mean, whitened bins) and
+    the overlap-add."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2511_04730_amd import Whitener
+    N, Z, D = 4 * WHITEN_RATE_IN, WHITEN_RATE_IN, WHITEN_RATE_IN // w.sample_rate
+    nd = w.n_detectors
+    wh = Whitener(nd, N, Z, D)
+    g = np.random.default_rng([w.config, 7, 0])
+    xs = [torch.from_numpy(g.standard_normal((nd, wh.hop)).astype(np.float32)).cuda() for _ in range(4)]
+    out = torch.empty((nd, wh.hop_out), dtype=torch.float32, device="cuda")
+    for i in range(8):
+        wh.push(xs[i % 4], out=out)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for i in range(reps):
+        wh.push(xs[i % 4], out=out)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    finite = bool(torch.isfinite(out).all().item())
+    n_out, K, H = N // D, N // D // 2 + 1, wh.hop
+    per_det = (8 * H + 4 * H + 8 * N + 16 * N * int(math.log2(N)) + 16 * n_out * int(math.log2(n_out))
+               + K * (8 + 4 * 7 + 4 + 8 + 8) + n_out * (8 + 4 + 4 + 4) + 4 * (H // D))
+    launches = 3 + int(math.log2(N)) + int(math.log2(n_out))
+    wh.close()
+    return {"ms_per_push": ms, "block": N, "pad": Z, "decimation": D, "rate_in_hz": WHITEN_RATE_IN,
+            "launches_per_push": launches, "bytes": per_det * nd, "finite": finite}
+
+
 def parity_and_baseline(plan, w, x, strides, k: int, seconds: float):
     """Oracle (FP64, host cores) on detector 0 for stride k of as many banks
     as fit in `seconds`; GPU series of the same banks and stride from a fresh
@@ -246,7 +290,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--xi2", type=int, default=-1,
-                    help="also time xi^2 and coincidence on the triggers (-1: all workloads but the largest)")
+                    help="also time xi^2, coincidence and whitening (-1: all workloads but the largest)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -333,6 +377,14 @@ def main() -> int:
         log(f"xi2: {m['ms']:.4f} ms per launch, {gbs:.0f} GB/s; window triggers {m['trig_ms']:.4f} ms, "
             f"coincidence {m['coinc_ms']:.4f} ms, {m['events']} banks with an event")
 
+    whiten = None
+    if args.xi2 == 1 or (args.xi2 == -1 and args.workload != "largest"):
+        m = whiten_measure(w, min(steps, 16))
+        gbs = m.pop("bytes") / (m["ms_per_push"] / 1e3) / 1e9
+        whiten = dict(m, roofline={"bound": "hbm", "kernel": "whitening push", "achieved": gbs, "peak": HBM_GBS,
+                                   "unit": "GB/s", "frac": gbs / HBM_GBS})
+        log(f"whitening: {m['ms_per_push']:.4f} ms per push ({m['launches_per_push']} launches), {gbs:.0f} GB/s")
+
     base = err = None
     if not args.no_cpu_baseline:
         base, err, nb = parity_and_baseline(plan, w, x, strides, k_par, args.cpu_seconds)
@@ -367,6 +419,7 @@ def main() -> int:
         "kernel_ms": kernel_ms,
         "xi2": xi2,
         "coincidence": coinc,
+        "whitening": whiten,
         "snr_err": err,
         "compare": compare,
         "cpu_baseline": base,

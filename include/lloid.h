@@ -345,6 +345,54 @@ lloid_status lloid_coincidence(lloid_plan *plan, const float *prev_dev, const ll
                                const int32_t *window, lloid_peak *triggers_dev, lloid_event *events_dev,
                                void *stream);
 
+/* PSD estimation and whitening with frequency-domain downsampling
+ * (Sec. II.B.2), upstream of the filter; one whitener serves n_detectors
+ * streams.  Each push takes H = N/2 - Z new samples per detector at the
+ * input rate and returns H/D whitened samples at the output rate:
+ *   - the last 2H inputs times the periodic Hann window sin^2(pi m / 2H)
+ *     (which sums to one at hop H), zero-padded by Z on each side, go
+ *     through an N-point FFT; only the first N/(2D) + 1 bins are kept
+ *     (downsampling by D in the frequency domain);
+ *   - per bin the instantaneous PSD |X|^2 / sum(hann^2) joins the last
+ *     n_med estimates; the median of the most recent c of them (c the
+ *     largest odd count available) over beta_c, the median-to-geometric-mean
+ *     ratio of chi^2_2 bins, updates a running average of the log over
+ *     min(blocks seen, n_avg) blocks; PSD = geometric mean x e^gamma,
+ *     including the current block;
+ *   - X / sqrt(D PSD) goes through the N/D-point inverse FFT (real DC and
+ *     Nyquist bins), is tapered by a Tukey window that is one over the
+ *     segment and a raised cosine over each Z/D-sample pad, and is
+ *     overlap-added; the first H/D accumulated samples are the output.
+ * Push i = 1, 2, ... returns the whitened input times [iH - 2H - Z,
+ * iH - H - Z): a latency of N/2 input samples.  White noise comes out with
+ * unit variance at every D.
+ * A detector whose gap_mask bit is set adds no block and no PSD estimate
+ * for that push (its input is taken as zeros for later blocks); its
+ * accumulator keeps draining.
+ *   config       n_detectors 1..32; block N a power of two, 64..2^20; pad Z
+ *                with 0 <= 4Z <= N; decimation D a power of two dividing Z
+ *                and H with N/D >= 16; n_med odd, 1..15; n_avg >= 1
+ *   in_dev       device [n_det][H] float32
+ *   out_dev      device [n_det][H/D] float32
+ *   psd_dev      device [n_det][N/(2D) + 1] float32: the current PSD
+ *                (per-sample variance units)
+ * Errors: LLOID_E_ARG, LLOID_E_SHAPE, LLOID_E_NOMEM, LLOID_E_HIP.  Create
+ * synchronises `stream`; push and psd only enqueue on it. */
+typedef struct lloid_whitener lloid_whitener;
+typedef struct {
+    int32_t n_detectors;
+    int32_t block;
+    int32_t pad;
+    int32_t decimation;
+    int32_t n_med;
+    int32_t n_avg;
+} lloid_whiten_config;
+lloid_status lloid_whitener_create(const lloid_whiten_config *config, void *stream, lloid_whitener **whitener);
+void lloid_whitener_destroy(lloid_whitener *whitener);
+lloid_status lloid_whitener_push(lloid_whitener *whitener, const float *in_dev, uint32_t gap_mask, float *out_dev,
+                                 void *stream);
+lloid_status lloid_whitener_psd(lloid_whitener *whitener, float *psd_dev, void *stream);
+
 /* Per-kernel timing of lloid_push_stride with HIP events recorded on the
  * call's stream around each of the stride's kernels:
  *   0 ingest, 1 decimation, 2 basis correlation, 3 split reduction,

@@ -641,7 +641,7 @@ class Whitener:
     and returns H / D whitened output samples."""
 
     def __init__(self, n: int, z: int, d: int = 1, n_med: int = 7, n_avg: int = 64):
-        assert n & (n - 1) == 0 and 0 <= z < n // 4 and n % d == 0 and z % d == 0 and n_med % 2 == 1
+        assert n & (n - 1) == 0 and 0 <= z <= n // 4 and n % d == 0 and z % d == 0 and n_med % 2 == 1
         self.n, self.z, self.d, self.n_med, self.n_avg = n, z, d, n_med, n_avg
         self.h = n // 2 - z
         assert self.h % d == 0

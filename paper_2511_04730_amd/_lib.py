@@ -48,6 +48,11 @@ class Config(ctypes.Structure):
                 ("normalize", ctypes.c_int32), ("snr_threshold", ctypes.c_float)]
 
 
+class WhitenConfig(ctypes.Structure):
+    _fields_ = [("n_detectors", ctypes.c_int32), ("block", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("decimation", ctypes.c_int32), ("n_med", ctypes.c_int32), ("n_avg", ctypes.c_int32)]
+
+
 class Peak(ctypes.Structure):
     _fields_ = [("snr", ctypes.c_float), ("index", ctypes.c_int32), ("re", ctypes.c_float),
                 ("im", ctypes.c_float), ("above", ctypes.c_int32)]
@@ -92,6 +97,14 @@ def load() -> ctypes.CDLL:
     lib.lloid_xi2.restype = ctypes.c_int
     lib.lloid_coincidence.argtypes = [P, P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), P, P, P]
     lib.lloid_coincidence.restype = ctypes.c_int
+    lib.lloid_whitener_create.argtypes = [ctypes.POINTER(WhitenConfig), P, ctypes.POINTER(P)]
+    lib.lloid_whitener_create.restype = ctypes.c_int
+    lib.lloid_whitener_destroy.argtypes = [P]
+    lib.lloid_whitener_destroy.restype = None
+    lib.lloid_whitener_push.argtypes = [P, P, ctypes.c_uint32, P, P]
+    lib.lloid_whitener_push.restype = ctypes.c_int
+    lib.lloid_whitener_psd.argtypes = [P, P, P]
+    lib.lloid_whitener_psd.restype = ctypes.c_int
     lib.lloid_set_option.argtypes = [P, ctypes.c_int32, ctypes.c_int64]
     lib.lloid_set_option.restype = ctypes.c_int
     lib.lloid_status_string.argtypes = [ctypes.c_int]

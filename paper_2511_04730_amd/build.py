@@ -13,7 +13,8 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblloid.so")
 SOURCES = ["lloid_plan.hip", "lloid_kernels.hip", "lloid_corr.hip", "lloid_mix.hip", "lloid_grad.hip",
-           "lloid_xi2.hip", "lloid_coinc.hip"]
+           "lloid_xi2.hip", "lloid_coinc.hip",
+           "lloid_whiten.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

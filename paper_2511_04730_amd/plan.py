@@ -307,3 +307,52 @@ def orthonormalize(U, W, stream=None) -> None:
     L.check(lib.lloid_orthonormalize(ctypes.c_void_p(U.data_ptr()), U.shape[0], U.shape[1],
                                      ctypes.c_void_p(W.data_ptr()), W.shape[0], _stream_handle(stream)),
             "lloid_orthonormalize")
+
+
+class Whitener:
+    """PSD estimation and whitening with frequency-domain downsampling for
+    n_detectors streams (lloid_whitener_*): push() takes H = block/2 - pad
+    new samples per detector and returns H / decimation whitened ones."""
+
+    def __init__(self, n_detectors: int, block: int, pad: int, decimation: int = 1, n_med: int = 7,
+                 n_avg: int = 64, stream=None):
+        self.lib = L.load()
+        self.n_detectors, self.block, self.pad, self.decimation = n_detectors, block, pad, decimation
+        self.hop = block // 2 - pad
+        self.hop_out = self.hop // decimation
+        self.bins = block // decimation // 2 + 1
+        cfg = L.WhitenConfig(n_detectors, block, pad, decimation, n_med, n_avg)
+        handle = ctypes.c_void_p()
+        L.check(self.lib.lloid_whitener_create(ctypes.byref(cfg), _stream_handle(stream), ctypes.byref(handle)),
+                "lloid_whitener_create")
+        self.handle = handle
+
+    def push(self, x, gap_mask: int = 0, out=None, stream=None):
+        """x: cuda float32 [n_det, hop]; returns cuda float32 [n_det, hop_out]."""
+        import torch
+        assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+        assert tuple(x.shape) == (self.n_detectors, self.hop)
+        if out is None:
+            out = torch.empty((self.n_detectors, self.hop_out), dtype=torch.float32, device="cuda")
+        L.check(self.lib.lloid_whitener_push(self.handle, ctypes.c_void_p(x.data_ptr()), int(gap_mask),
+                                             ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+                "lloid_whitener_push")
+        return out
+
+    def psd(self, stream=None):
+        import torch
+        out = torch.empty((self.n_detectors, self.bins), dtype=torch.float32, device="cuda")
+        L.check(self.lib.lloid_whitener_psd(self.handle, ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+                "lloid_whitener_psd")
+        return out
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            self.lib.lloid_whitener_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
