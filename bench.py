@@ -68,7 +68,8 @@ def workload(name: str):
 KERNEL_SOURCES = {"mix": ["lloid_mix.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
                   "corr": ["lloid_corr.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
                   "xi2": ["lloid_xi2.hip", "lloid_xi2.h", "lloid_internal.h", "lloid_device.h"],
-                  "window_trigger": ["lloid_coinc.hip", "lloid_coinc.h", "lloid_internal.h", "lloid_device.h"]}
+                  "window_trigger": ["lloid_coinc.hip", "lloid_coinc.h", "lloid_internal.h", "lloid_device.h"],
+                  "whitening": ["lloid_whiten.hip", "lloid_whiten.h"]}
 
 
 def source_digest(kernel: str) -> str:
@@ -205,9 +206,9 @@ def whiten_measure(w, reps: int):
     median of 7, for every detector.  Returns the mean HIP-event time of one
     push over `reps` pushes after 8 untimed ones, and its algorithmic bytes
     per detector: the Hann block (inputs read, complex block written), the
-    Stockham passes of both transforms (each reads and writes every complex
-    value), the PSD update (bins, median ring, log mean, whitened bins) and
-    the overlap-add."""
+    radix-4 Stockham passes of both transforms (each reads and writes every
+    complex value), the PSD update (bins, median ring, log mean, whitened
+    bins) and the overlap-add."""
     import math
     import numpy as np
     import torch
@@ -231,9 +232,10 @@ def whiten_measure(w, reps: int):
     ms = e0.elapsed_time(e1) / reps
     finite = bool(torch.isfinite(out).all().item())
     n_out, K, H = N // D, N // D // 2 + 1, wh.hop
-    per_det = (8 * H + 4 * H + 8 * N + 16 * N * int(math.log2(N)) + 16 * n_out * int(math.log2(n_out))
+    passes = lambda n: (int(math.log2(n)) + 1) // 2      # radix-4 passes (one radix-2 pass if log2 n is odd)
+    per_det = (8 * H + 4 * H + 8 * N + 16 * N * passes(N) + 16 * n_out * passes(n_out)
                + K * (8 + 4 * 7 + 4 + 8 + 8) + n_out * (8 + 4 + 4 + 4) + 4 * (H // D))
-    launches = 3 + int(math.log2(N)) + int(math.log2(n_out))
+    launches = 3 + passes(N) + passes(n_out)
     wh.close()
     return {"ms_per_push": ms, "block": N, "pad": Z, "decimation": D, "rate_in_hz": WHITEN_RATE_IN,
             "launches_per_push": launches, "bytes": per_det * nd, "finite": finite}
@@ -382,7 +384,8 @@ def main() -> int:
         m = whiten_measure(w, min(steps, 16))
         gbs = m.pop("bytes") / (m["ms_per_push"] / 1e3) / 1e9
         whiten = dict(m, roofline={"bound": "hbm", "kernel": "whitening push", "achieved": gbs, "peak": HBM_GBS,
-                                   "unit": "GB/s", "frac": gbs / HBM_GBS})
+                                   "unit": "GB/s", "frac": gbs / HBM_GBS,
+                                   "traffic": measured_traffic("whitening", args.workload, args.precision)})
         log(f"whitening: {m['ms_per_push']:.4f} ms per push ({m['launches_per_push']} launches), {gbs:.0f} GB/s")
 
     base = err = None

@@ -12,10 +12,10 @@
 // window and overlap-added; the first H/D samples of the accumulator are
 // the output.
 //
-// The FFTs are radix-2 Stockham passes through global memory (self-sorting,
-// one launch per pass, one butterfly per thread): the transforms are small
-// (at most a few hundred KB per detector) and latency- rather than
-// bandwidth-bound.
+// The FFTs are radix-4 Stockham passes through global memory (self-sorting,
+// one launch per pass, one 4-point butterfly per thread; one radix-2 pass
+// first when log2 N is odd): the transforms are small (at most a few
+// hundred KB per detector) and bound by launch latency, not bandwidth.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -72,6 +72,40 @@ __global__ void fft_pass_kernel(const f32x2 *__restrict__ src, f32x2 *__restrict
     const int o = ((j - k) << 1) + k;
     y[o] = a + wb;
     y[o + m] = a - wb;
+}
+
+// One radix-4 Stockham pass with sub-transform size m: reads j + q N/4
+// (q = 0..3), twiddles exp(sign 2 pi i q k / 4m), a 4-point DFT, writes
+// 4m floor(j/m) + (j mod m) + q m.
+__global__ void fft_pass4_kernel(const f32x2 *__restrict__ src, f32x2 *__restrict__ dst, int32_t N, int32_t m,
+                                 int32_t twstep, int32_t inverse, const f32x2 *__restrict__ tw) {
+    const int det = blockIdx.y;
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int Q = N / 4;
+    if (j >= Q) return;
+    const f32x2 *x = src + (int64_t)det * N;
+    f32x2 *y = dst + (int64_t)det * N;
+    const int k = j & (m - 1);
+    f32x2 a[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const f32x2 v = x[j + q * Q];
+        if (q == 0) {
+            a[0] = v;
+        } else {
+            f32x2 w = tw[(int64_t)q * k * twstep];
+            if (inverse) w.y = -w.y;
+            a[q] = f32x2{w.x * v.x - w.y * v.y, w.x * v.y + w.y * v.x};
+        }
+    }
+    const f32x2 b0 = a[0] + a[2], b1 = a[0] - a[2], b2 = a[1] + a[3], d = a[1] - a[3];
+    // (a1 - a3) times -i (forward) or +i (inverse)
+    const f32x2 b3 = inverse ? f32x2{-d.y, d.x} : f32x2{d.y, -d.x};
+    const int o = 4 * (j - k) + k;
+    y[o] = b0 + b2;
+    y[o + m] = b1 + b3;
+    y[o + 2 * m] = b0 - b2;
+    y[o + 3 * m] = b1 - b3;
 }
 
 // Per bin k < K = N_out/2 + 1: instantaneous PSD into the ring, running
@@ -159,9 +193,22 @@ hipError_t launch_whiten_block(hipStream_t st, const float *in, int64_t in_ld, c
 hipError_t launch_fft(hipStream_t st, void *a, void *b, int32_t N, int32_t N_table, int32_t inverse, const void *tw,
                       int32_t n_det, void **result) {
     f32x2 *src = static_cast<f32x2 *>(a), *dst = static_cast<f32x2 *>(b);
-    for (int m = 1; m < N; m <<= 1) {
-        hipLaunchKernelGGL(fft_pass_kernel, dim3((N / 2 + 255) / 256, n_det), dim3(256), 0, st, src, dst, N, m,
-                           N_table / (2 * m), inverse, static_cast<const f32x2 *>(tw));
+    int log2n = 0;
+    while ((1 << log2n) < N) ++log2n;
+    int m = 1;
+    if (log2n & 1) {                     // one radix-2 pass, then radix-4
+        hipLaunchKernelGGL(fft_pass_kernel, dim3((N / 2 + 255) / 256, n_det), dim3(256), 0, st, src, dst, N, 1,
+                           N_table / 2, inverse, static_cast<const f32x2 *>(tw));
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        f32x2 *t = src;
+        src = dst;
+        dst = t;
+        m = 2;
+    }
+    for (; m < N; m <<= 2) {
+        hipLaunchKernelGGL(fft_pass4_kernel, dim3((N / 4 + 255) / 256, n_det), dim3(256), 0, st, src, dst, N, m,
+                           N_table / (4 * m), inverse, static_cast<const f32x2 *>(tw));
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         f32x2 *t = src;
@@ -267,7 +314,7 @@ lloid_status lloid_whitener_create(const lloid_whiten_config *c, void *stream, l
     w->h_out = w->H / D;
     w->K = w->n_out / 2 + 1;
     const int H = w->H, n_out = w->n_out, zo = Z / D;
-    std::vector<float> hann(2 * H), tukey(n_out, 1.f), beta(kWhitenMaxMed + 1, 1.f), tw(N);
+    std::vector<float> hann(2 * H), tukey(n_out, 1.f), beta(kWhitenMaxMed + 1, 1.f), tw(2 * (size_t)N);
     const double pi = 3.14159265358979323846;
     double w2 = 0.0;
     for (int m = 0; m < 2 * H; ++m) {
@@ -282,12 +329,12 @@ lloid_status lloid_whitener_create(const lloid_whiten_config *c, void *stream, l
         tukey[n_out - 1 - n] = r;
     }
     for (int cc = 1; cc <= c->n_med; cc += 2) beta[cc] = (float)median_bias(cc);
-    for (int q = 0; q < N / 2; ++q) {
+    for (int q = 0; q < N; ++q) {         // the full circle: radix-4 passes index up to 3N/4
         tw[2 * q] = (float)std::cos(-2.0 * pi * q / N);
         tw[2 * q + 1] = (float)std::sin(-2.0 * pi * q / N);
     }
     bool ok = w->alloc(&w->hann, 2 * H) && w->alloc(&w->tukey, n_out) && w->alloc(&w->beta, kWhitenMaxMed + 1);
-    ok = ok && w->alloc(reinterpret_cast<float **>(&w->tw), N);
+    ok = ok && w->alloc(reinterpret_cast<float **>(&w->tw), 2 * (size_t)N);
     for (int i = 0; i < 2 && ok; ++i) {
         ok = w->alloc(&w->prev[i], (size_t)ND * H) && w->alloc(&w->acc[i], (size_t)ND * n_out) &&
              w->alloc(reinterpret_cast<float **>(&w->blk[i]), (size_t)ND * N * 2) &&
