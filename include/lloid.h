@@ -393,6 +393,17 @@ lloid_status lloid_whitener_push(lloid_whitener *whitener, const float *in_dev, 
                                  void *stream);
 lloid_status lloid_whitener_psd(lloid_whitener *whitener, float *psd_dev, void *stream);
 
+/* FP8 basis values for quantisation-aware refinement (extension): writes
+ * to Uq_dev the values the FP8_BF16 form correlates with for the rows of
+ * U_dev (device float64 [rows][cols], row-major; Uq_dev the same shape,
+ * may not alias): per row a power-of-two scale 2^e with e =
+ * floor(log2(448 / max|u|)), e4m3 (OCP, round to nearest even) of the
+ * float32-rounded u 2^e, times 2^-e.  A refinement that evaluates the loss
+ * of an FP32 plan at these values and applies the gradient to U (straight
+ * through the rounding) optimises the bank for the FP8 form.  Enqueues on
+ * `stream`.  Errors: LLOID_E_ARG, LLOID_E_HIP. */
+lloid_status lloid_quantize_fp8_rows(const double *U_dev, int32_t rows, int32_t cols, double *Uq_dev, void *stream);
+
 /* Per-kernel timing of lloid_push_stride with HIP events recorded on the
  * call's stream around each of the stride's kernels:
  *   0 ingest, 1 decimation, 2 basis correlation, 3 split reduction,

@@ -21,6 +21,8 @@ primitives:
                        events across detectors, one event per sub-bank
   whitening         -- Sec. II.B.2: PSD estimation and whitening with
                        frequency-domain downsampling
+  FP8 basis values  -- the e4m3 rounding of the FP8 form (extension), for
+                       quantisation-aware refinement
 
 Readings of points the paper leaves open are stated where they are used:
 
@@ -689,3 +691,31 @@ class Whitener:
         out = self.acc[:self.h_out].copy()
         self.acc = np.concatenate([self.acc[self.h_out:], np.zeros(self.h_out)])
         return out
+
+
+# ---------------------------------------------------------------------------
+# FP8 basis values for quantisation-aware refinement (extension; reading 19)
+# ---------------------------------------------------------------------------
+
+def e4m3_round(x: np.ndarray) -> np.ndarray:
+    """Nearest OCP e4m3 value (4 exponent bits, bias 7, 3 mantissa bits,
+    subnormals below 2^-6, largest finite 448), ties to the even mantissa;
+    |x| <= 448.  In a binade [2^e, 2^(e+1)) the spacing is 2^(e-3); below
+    2^-6 it is 2^-9."""
+    x = np.asarray(x, np.float64)
+    a = np.abs(x)
+    e = np.clip(np.floor(np.log2(np.where(a > 0, a, 1.0))), -6, 8)
+    q = 2.0 ** (e - 3)
+    return np.sign(x) * np.round(a / q) * q          # np.round: half to even
+
+
+def quantize_fp8_rows(U: np.ndarray) -> np.ndarray:
+    """The basis values the FP8 form correlates with, as float64: per row a
+    power-of-two scale 2^e, e = floor(log2(448 / max|u|)), then e4m3 of the
+    float32-rounded u 2^e (the precision the GPU rounds from), times 2^-e."""
+    U = np.asarray(U, np.float64)
+    mx = np.abs(U).max(axis=1)
+    e = np.where(mx > 0, np.floor(np.log2(448.0 / np.where(mx > 0, mx, 1.0))), 0.0)
+    s = 2.0 ** e
+    x32 = (U * s[:, None]).astype(np.float32).astype(np.float64)
+    return e4m3_round(x32) / s[:, None]

@@ -288,3 +288,42 @@ hipError_t launch_cholesky_qr2(hipStream_t st, double *U, int32_t L, int32_t N, 
 }
 
 }  // namespace lloid
+
+// ------------------------------------------- FP8 basis values (refinement)
+// The values the FP8 form's correlation uses for a basis row, as float64:
+// one block per row, e = floor(log2(448 / max|u|)), e4m3 (round to nearest
+// even, from float32) of u 2^e, times 2^-e.  Quantisation-aware refinement
+// evaluates the loss at these values and applies the gradient to the
+// unrounded rows.
+namespace {
+
+__global__ __launch_bounds__(256) void quantize_fp8_rows_kernel(const double *__restrict__ src, int32_t cols,
+                                                                double *__restrict__ dst) {
+    __shared__ double red[256];
+    const int r = blockIdx.x;
+    const double *u = src + (int64_t)r * cols;
+    double mx = 0.0;
+    for (int c = threadIdx.x; c < cols; c += 256) mx = fmax(mx, fabs(u[c]));
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+        __syncthreads();
+    }
+    const int e = red[0] > 0.0 ? (int)floor(log2(448.0 / red[0])) : 0;
+    const double s = ldexp(1.0, e);
+    for (int c = threadIdx.x; c < cols; c += 256) {
+        const uint32_t b = (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32((float)(u[c] * s), 0.0f, 0, false) & 0xffu;
+        dst[(int64_t)r * cols + c] = ldexp((double)__builtin_amdgcn_cvt_f32_fp8((int)b, 0), -e);
+    }
+}
+
+}  // namespace
+
+extern "C" lloid_status lloid_quantize_fp8_rows(const double *U, int32_t rows, int32_t cols, double *Uq,
+                                                void *stream) {
+    if (!U || !Uq || rows < 1 || cols < 1) return LLOID_E_ARG;
+    hipLaunchKernelGGL(quantize_fp8_rows_kernel, dim3(rows), dim3(256), 0, static_cast<hipStream_t>(stream), U, cols,
+                       Uq);
+    return hipGetLastError() == hipSuccess ? LLOID_OK : LLOID_E_HIP;
+}

@@ -296,6 +296,19 @@ class LloidPlan:
         return self.inspect(L.INSPECT_BASIS_OUT, slice_index, det, m_lo, m_hi, rows=n_basis)
 
 
+def quantize_fp8_rows(U, stream=None):
+    """The FP8 form's basis values for U (cuda float64 [L, N]) as a new
+    cuda float64 tensor (lloid_quantize_fp8_rows)."""
+    import torch
+    assert U.is_cuda and U.dtype == torch.float64 and U.dim() == 2
+    U = U.contiguous()
+    out = torch.empty_like(U)
+    L.check(L.load().lloid_quantize_fp8_rows(ctypes.c_void_p(U.data_ptr()), U.shape[0], U.shape[1],
+                                             ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)),
+            "lloid_quantize_fp8_rows")
+    return out
+
+
 def orthonormalize(U, W, stream=None) -> None:
     """FP64 CholeskyQR2 on the device, in place: U (cuda float64 [L, N])
     gets orthonormal rows and W (cuda float64 [rows, L]) is updated so that
