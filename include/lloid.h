@@ -393,6 +393,25 @@ lloid_status lloid_whitener_push(lloid_whitener *whitener, const float *in_dev, 
                                  void *stream);
 lloid_status lloid_whitener_psd(lloid_whitener *whitener, float *psd_dev, void *stream);
 
+/* SVD bank construction (Sec. II.C.1) for one time slice: the rank-L
+ * truncation of the slice's template matrix H (device float64 [rows][N],
+ * rows = 2M real templates in the slice's samples) as basis rows U and
+ * mixing rows W with W U = H P_L, P_L the projector on the top-L right
+ * singular subspace (the best rank-L approximation, as the truncated SVD
+ * gives; the basis is an orthonormal basis of that subspace, not
+ * necessarily the singular vectors themselves).  Subspace iteration
+ * U <- orth((H^T H) U), CholeskyQR2 after each product, `iters` times;
+ * the error shrinks by (sigma_{L+1} / sigma_L)^2 per iteration.
+ *   U_dev  device float64 [L][N]: in, the starting rows (for instance
+ *          seeded Gaussian); out, the orthonormal basis
+ *   W_dev  device float64 [rows][L]: out, H U^T
+ * 1 <= L <= min(160, rows, N).  Synchronises `stream`.
+ * Errors: LLOID_E_ARG, LLOID_E_NOMEM, LLOID_E_STATE (the iterated rows
+ * became linearly dependent: a start without components in the subspace,
+ * or a rank of H below L), LLOID_E_HIP. */
+lloid_status lloid_svd_basis(const double *H_dev, int32_t rows, int32_t N, int32_t L, int32_t iters, double *U_dev,
+                             double *W_dev, void *stream);
+
 /* FP8 basis values for quantisation-aware refinement (extension): writes
  * to Uq_dev the values the FP8_BF16 form correlates with for the rows of
  * U_dev (device float64 [rows][cols], row-major; Uq_dev the same shape,

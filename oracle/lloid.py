@@ -719,3 +719,16 @@ def quantize_fp8_rows(U: np.ndarray) -> np.ndarray:
     s = 2.0 ** e
     x32 = (U * s[:, None]).astype(np.float32).astype(np.float64)
     return e4m3_round(x32) / s[:, None]
+
+
+# ---------------------------------------------------------------------------
+# SVD bank construction (Sec. II.C.1)
+# ---------------------------------------------------------------------------
+
+def svd_truncate(H: np.ndarray, L: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Rank-L truncated SVD of a slice's template matrix H [2M, N] (NumPy's
+    SVD as the library step): basis rows U = the first L right singular
+    vectors, mixing W = (left singular vectors x singular values)[:, :L], so
+    W U is the best rank-L approximation of H."""
+    Ul, sv, Vt = np.linalg.svd(np.asarray(H, np.float64), full_matrices=False)
+    return Vt[:L].copy(), Ul[:, :L] * sv[:L]

@@ -105,6 +105,8 @@ def load() -> ctypes.CDLL:
     lib.lloid_whitener_push.restype = ctypes.c_int
     lib.lloid_whitener_psd.argtypes = [P, P, P]
     lib.lloid_whitener_psd.restype = ctypes.c_int
+    lib.lloid_svd_basis.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P, P, P]
+    lib.lloid_svd_basis.restype = ctypes.c_int
     lib.lloid_quantize_fp8_rows.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P]
     lib.lloid_quantize_fp8_rows.restype = ctypes.c_int
     lib.lloid_set_option.argtypes = [P, ctypes.c_int32, ctypes.c_int64]

@@ -327,3 +327,83 @@ extern "C" lloid_status lloid_quantize_fp8_rows(const double *U, int32_t rows, i
                        Uq);
     return hipGetLastError() == hipSuccess ? LLOID_OK : LLOID_E_HIP;
 }
+
+// ------------------------------------------------ SVD bank construction
+// The rank-L truncation of a slice's template matrix H (rows x N, float64)
+// by subspace iteration: V <- orth((H^T H) V) with CholeskyQR2 after every
+// product; V's rows converge to an orthonormal basis of the top-L right
+// singular subspace (error ratio (sigma_{L+1} / sigma_L)^2 per iteration),
+// and W = H V^T, so that W V = H P_L, the best rank-L approximation.
+namespace {
+
+// T[r][l] = sum_n H[r][n] V[l][n]: one block per (r, l)
+__global__ __launch_bounds__(256) void h_vt_kernel(const double *__restrict__ H, const double *__restrict__ V,
+                                                   int32_t N, int32_t L, double *__restrict__ T) {
+    __shared__ double red[256];
+    const int r = blockIdx.x, l = blockIdx.y;
+    double s = 0.0;
+    for (int n = threadIdx.x; n < N; n += 256) s += H[(int64_t)r * N + n] * V[(int64_t)l * N + n];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) T[(int64_t)r * L + l] = red[0];
+}
+
+// V[l][n] = sum_r T[r][l] H[r][n]: one thread per (l, n)
+__global__ __launch_bounds__(256) void ht_t_kernel(const double *__restrict__ H, const double *__restrict__ T,
+                                                   int32_t rows, int32_t N, int32_t L, double *__restrict__ V) {
+    const int n = blockIdx.x * 256 + threadIdx.x, l = blockIdx.y;
+    if (n >= N) return;
+    double s = 0.0;
+    for (int r = 0; r < rows; ++r) s += T[(int64_t)r * L + l] * H[(int64_t)r * N + n];
+    V[(int64_t)l * N + n] = s;
+}
+
+}  // namespace
+
+extern "C" lloid_status lloid_svd_basis(const double *H, int32_t rows, int32_t N, int32_t L, int32_t iters, double *U,
+                                        double *W, void *stream) {
+    if (!H || !U || !W || rows < 1 || N < 1 || L < 1 || L > lloid::kMaxBasis || L > rows || L > N || iters < 1)
+        return LLOID_E_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double *T = nullptr, *G = nullptr, *dummy = nullptr;
+    int32_t *info = nullptr;
+    if (hipMalloc(&T, sizeof(double) * rows * L) != hipSuccess) return LLOID_E_NOMEM;
+    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess || hipMalloc(&dummy, sizeof(double) * L) != hipSuccess ||
+        hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess) {
+        (void)hipFree(T);
+        (void)hipFree(G);
+        (void)hipFree(dummy);
+        return LLOID_E_NOMEM;
+    }
+    int32_t h[2] = {0, 0}, bad = 0;
+    hipError_t e = lloid::launch_cholesky_qr2(st, U, L, N, dummy, 1, G, info);   // orthonormal start
+    for (int it = 0; it < iters && e == hipSuccess; ++it) {
+        hipLaunchKernelGGL(h_vt_kernel, dim3(rows, L), dim3(256), 0, st, H, U, N, L, T);
+        hipLaunchKernelGGL(ht_t_kernel, dim3((N + 255) / 256, L), dim3(256), 0, st, H, T, rows, N, L, U);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = lloid::launch_cholesky_qr2(st, U, L, N, dummy, 1, G, info);
+        if (e == hipSuccess && (it % 16 == 15 || it == iters - 1)) {   // a singular block stops the iteration
+            e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (h[0] || h[1]) {
+                bad = 1;
+                break;
+            }
+        }
+    }
+    if (e == hipSuccess && !bad) {
+        hipLaunchKernelGGL(h_vt_kernel, dim3(rows, L), dim3(256), 0, st, H, U, N, L, W);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+    }
+    (void)hipFree(T);
+    (void)hipFree(G);
+    (void)hipFree(dummy);
+    (void)hipFree(info);
+    if (e != hipSuccess) return LLOID_E_HIP;
+    return bad ? LLOID_E_STATE : LLOID_OK;
+}

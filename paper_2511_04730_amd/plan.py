@@ -296,6 +296,23 @@ class LloidPlan:
         return self.inspect(L.INSPECT_BASIS_OUT, slice_index, det, m_lo, m_hi, rows=n_basis)
 
 
+def svd_basis(H, rank: int, start, iters: int = 200, stream=None):
+    """Rank-`rank` truncation of a slice's template matrix H (cuda float64
+    [rows, N]) on the GPU (lloid_svd_basis): returns (U [rank, N],
+    orthonormal rows spanning the top right singular subspace, and
+    W = H U^T [rows, rank]).  start: cuda float64 [rank, N] starting rows
+    (seeded Gaussian, say)."""
+    import torch
+    assert H.is_cuda and H.dtype == torch.float64 and tuple(start.shape) == (rank, H.shape[1])
+    H = H.contiguous()
+    U = start.detach().clone().contiguous()
+    W = torch.empty((H.shape[0], rank), dtype=torch.float64, device="cuda")
+    L.check(L.load().lloid_svd_basis(ctypes.c_void_p(H.data_ptr()), H.shape[0], H.shape[1], rank, iters,
+                                     ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(W.data_ptr()),
+                                     _stream_handle(stream)), "lloid_svd_basis")
+    return U, W
+
+
 def quantize_fp8_rows(U, stream=None):
     """The FP8 form's basis values for U (cuda float64 [L, N]) as a new
     cuda float64 tensor (lloid_quantize_fp8_rows)."""
