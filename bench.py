@@ -241,6 +241,33 @@ def whiten_measure(w, reps: int):
             "launches_per_push": launches, "bytes": per_det * nd, "finite": finite}
 
 
+def svd_measure(reps: int = 3, rows: int = 2048, n: int = 1024, rank: int = 40, iters: int = 30):
+    """SVD bank construction (Sec. II.C.1) for one slice of the realistic
+    bank's shape (2M = 2048 real templates, N = 1024 taps, L = 40): a seeded
+    matrix with a geometrically decaying spectrum, `iters` subspace
+    iterations, mean wall time over `reps` calls (each synchronises).
+    Algorithmic flops per call: iters x (2 products of 2 rows N L + two
+    CholeskyQR passes of 2 L^2 N + L^3 / 3) + the final product."""
+    import numpy as np
+    import torch
+    from paper_2511_04730_amd.plan import svd_basis
+    g = np.random.default_rng([42, 11, 0])
+    A = np.linalg.qr(g.standard_normal((rows, rank * 2)))[0]
+    B = np.linalg.qr(g.standard_normal((n, rank * 2)))[0]
+    H = torch.from_numpy((A * 0.8 ** np.arange(rank * 2)) @ B.T).cuda()
+    start = torch.from_numpy(g.standard_normal((rank, n))).cuda()
+    svd_basis(H, rank, start, iters=iters)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        svd_basis(H, rank, start, iters=iters)
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    flops = iters * (4 * rows * n * rank + 2 * (2 * rank * rank * n + rank ** 3 / 3)) + 2 * rows * n * rank
+    return {"ms": ms, "rows": rows, "taps": n, "rank": rank, "iterations": iters,
+            "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": flops / (ms / 1e3) / 1e12 / 78.6}}
+
+
 def parity_and_baseline(plan, w, x, strides, k: int, seconds: float):
     """Oracle (FP64, host cores) on detector 0 for stride k of as many banks
     as fit in `seconds`; GPU series of the same banks and stride from a fresh
@@ -292,7 +319,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--xi2", type=int, default=-1,
-                    help="also time xi^2, coincidence and whitening (-1: all workloads but the largest)")
+                    help="also time xi^2, coincidence, whitening and SVD construction (-1: all but the largest workload)")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -388,6 +415,11 @@ def main() -> int:
                                    "traffic": measured_traffic("whitening", args.workload, args.precision)})
         log(f"whitening: {m['ms_per_push']:.4f} ms per push ({m['launches_per_push']} launches), {gbs:.0f} GB/s")
 
+    svd = None
+    if args.xi2 == 1 or (args.xi2 == -1 and args.workload != "largest"):
+        svd = svd_measure()
+        log(f"svd bank construction: {svd['ms']:.2f} ms per slice")
+
     base = err = None
     if not args.no_cpu_baseline:
         base, err, nb = parity_and_baseline(plan, w, x, strides, k_par, args.cpu_seconds)
@@ -423,6 +455,7 @@ def main() -> int:
         "xi2": xi2,
         "coincidence": coinc,
         "whitening": whiten,
+        "svd_bank": svd,
         "snr_err": err,
         "compare": compare,
         "cpu_baseline": base,
