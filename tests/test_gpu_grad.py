@@ -118,7 +118,7 @@ def test_autograd_function_returns_library_gradient(lib, problem):
     l2, dW, dU = plan.grad(xs, tg)
     assert float(loss.detach()) == l2
     L_ref, _, _ = O.loss_and_grad(x[0], bank, target, cfg, 0, T * F)
-    assert abs(float(loss) - L_ref) <= 1e-4 * L_ref
+    assert abs(float(loss.detach()) - L_ref) <= 1e-4 * L_ref
     for i in range(len(U)):
         assert torch.equal(U[i].grad, 3.0 * dU[i].double())
         assert torch.equal(W[i].grad, 3.0 * dW[i].double())
