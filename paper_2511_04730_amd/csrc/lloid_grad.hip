@@ -280,7 +280,8 @@ hipError_t launch_cholesky_qr2(hipStream_t st, double *U, int32_t L, int32_t N, 
         hipLaunchKernelGGL(gram_f64_kernel, dim3(L, L), dim3(256), 0, st, U, L, N, G);
         hipLaunchKernelGGL(cholesky_f64_kernel, dim3(1), dim3(256), 0, st, G, L, info + pass);
         hipLaunchKernelGGL(trsm_lower_f64_kernel, dim3((N + 255) / 256), dim3(256), 0, st, G, L, U, N);
-        hipLaunchKernelGGL(right_mul_f64_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, W, rows, L, G);
+        if (rows > 0)   // rows == 0: orthonormalise U alone
+            hipLaunchKernelGGL(right_mul_f64_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, W, rows, L, G);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -369,23 +370,21 @@ extern "C" lloid_status lloid_svd_basis(const double *H, int32_t rows, int32_t N
     if (!H || !U || !W || rows < 1 || N < 1 || L < 1 || L > lloid::kMaxBasis || L > rows || L > N || iters < 1)
         return LLOID_E_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    double *T = nullptr, *G = nullptr, *dummy = nullptr;
+    double *T = nullptr, *G = nullptr;
     int32_t *info = nullptr;
     if (hipMalloc(&T, sizeof(double) * rows * L) != hipSuccess) return LLOID_E_NOMEM;
-    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess || hipMalloc(&dummy, sizeof(double) * L) != hipSuccess ||
-        hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess) {
+    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess || hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess) {
         (void)hipFree(T);
         (void)hipFree(G);
-        (void)hipFree(dummy);
         return LLOID_E_NOMEM;
     }
     int32_t h[2] = {0, 0}, bad = 0;
-    hipError_t e = lloid::launch_cholesky_qr2(st, U, L, N, dummy, 1, G, info);   // orthonormal start
+    hipError_t e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);   // orthonormal start
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
         hipLaunchKernelGGL(h_vt_kernel, dim3(rows, L), dim3(256), 0, st, H, U, N, L, T);
         hipLaunchKernelGGL(ht_t_kernel, dim3((N + 255) / 256, L), dim3(256), 0, st, H, T, rows, N, L, U);
         e = hipGetLastError();
-        if (e == hipSuccess) e = lloid::launch_cholesky_qr2(st, U, L, N, dummy, 1, G, info);
+        if (e == hipSuccess) e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);
         if (e == hipSuccess && (it % 16 == 15 || it == iters - 1)) {   // a singular block stops the iteration
             e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -402,7 +401,6 @@ extern "C" lloid_status lloid_svd_basis(const double *H, int32_t rows, int32_t N
     }
     (void)hipFree(T);
     (void)hipFree(G);
-    (void)hipFree(dummy);
     (void)hipFree(info);
     if (e != hipSuccess) return LLOID_E_HIP;
     return bad ? LLOID_E_STATE : LLOID_OK;
