@@ -353,14 +353,27 @@ __global__ __launch_bounds__(256) void h_vt_kernel(const double *__restrict__ H,
     if (threadIdx.x == 0) T[(int64_t)r * L + l] = red[0];
 }
 
-// V[l][n] = sum_r T[r][l] H[r][n]: one thread per (l, n)
+// part[p][l][n] = sum over rows r of split p of T[r][l] H[r][n]: one thread
+// per (l, n, p), so that the product fills the chip for few basis rows
+constexpr int kSvdSplit = 16;
 __global__ __launch_bounds__(256) void ht_t_kernel(const double *__restrict__ H, const double *__restrict__ T,
-                                                   int32_t rows, int32_t N, int32_t L, double *__restrict__ V) {
-    const int n = blockIdx.x * 256 + threadIdx.x, l = blockIdx.y;
+                                                   int32_t rows, int32_t N, int32_t L, double *__restrict__ part) {
+    const int n = blockIdx.x * 256 + threadIdx.x, l = blockIdx.y, p = blockIdx.z;
     if (n >= N) return;
+    const int r0 = (int)((int64_t)rows * p / kSvdSplit), r1 = (int)((int64_t)rows * (p + 1) / kSvdSplit);
     double s = 0.0;
-    for (int r = 0; r < rows; ++r) s += T[(int64_t)r * L + l] * H[(int64_t)r * N + n];
-    V[(int64_t)l * N + n] = s;
+    for (int r = r0; r < r1; ++r) s += T[(int64_t)r * L + l] * H[(int64_t)r * N + n];
+    part[((int64_t)p * L + l) * N + n] = s;
+}
+
+// V[l][n] = sum_p part[p][l][n] in a fixed order
+__global__ __launch_bounds__(256) void sum_splits_kernel(const double *__restrict__ part, int64_t plane,
+                                                         double *__restrict__ V) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= plane) return;
+    double s = 0.0;
+    for (int p = 0; p < kSvdSplit; ++p) s += part[p * plane + i];
+    V[i] = s;
 }
 
 }  // namespace
@@ -370,19 +383,24 @@ extern "C" lloid_status lloid_svd_basis(const double *H, int32_t rows, int32_t N
     if (!H || !U || !W || rows < 1 || N < 1 || L < 1 || L > lloid::kMaxBasis || L > rows || L > N || iters < 1)
         return LLOID_E_ARG;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    double *T = nullptr, *G = nullptr;
+    double *T = nullptr, *G = nullptr, *part = nullptr;
     int32_t *info = nullptr;
+    const int64_t plane = (int64_t)L * N;
     if (hipMalloc(&T, sizeof(double) * rows * L) != hipSuccess) return LLOID_E_NOMEM;
-    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess || hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess) {
+    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess || hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess ||
+        hipMalloc(&part, sizeof(double) * kSvdSplit * plane) != hipSuccess) {
         (void)hipFree(T);
         (void)hipFree(G);
+        (void)hipFree(info);
         return LLOID_E_NOMEM;
     }
     int32_t h[2] = {0, 0}, bad = 0;
     hipError_t e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);   // orthonormal start
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
         hipLaunchKernelGGL(h_vt_kernel, dim3(rows, L), dim3(256), 0, st, H, U, N, L, T);
-        hipLaunchKernelGGL(ht_t_kernel, dim3((N + 255) / 256, L), dim3(256), 0, st, H, T, rows, N, L, U);
+        hipLaunchKernelGGL(ht_t_kernel, dim3((N + 255) / 256, L, kSvdSplit), dim3(256), 0, st, H, T, rows, N, L,
+                           part);
+        hipLaunchKernelGGL(sum_splits_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, part, plane, U);
         e = hipGetLastError();
         if (e == hipSuccess) e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);
         if (e == hipSuccess && (it % 16 == 15 || it == iters - 1)) {   // a singular block stops the iteration
@@ -402,6 +420,7 @@ extern "C" lloid_status lloid_svd_basis(const double *H, int32_t rows, int32_t N
     (void)hipFree(T);
     (void)hipFree(G);
     (void)hipFree(info);
+    (void)hipFree(part);
     if (e != hipSuccess) return LLOID_E_HIP;
     return bad ? LLOID_E_STATE : LLOID_OK;
 }
