@@ -223,6 +223,37 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
 
 // In-place lower Cholesky factor C (G = C C^T) of an L x L SPD matrix, one
 // work group, column by column; info[0] = 0 or the failing column + 1.
+// The same factorisation with G held in LDS, for L <= kCholLds (the column
+// updates then read LDS instead of global memory).
+constexpr int kCholLds = 88;   // 88^2 doubles = 61952 bytes of static LDS
+__global__ __launch_bounds__(256) void cholesky_lds_f64_kernel(double *__restrict__ G, int32_t L, int32_t *info) {
+    __shared__ double sG[kCholLds * kCholLds];
+    __shared__ double piv;
+    for (int e = threadIdx.x; e < L * L; e += 256) sG[e] = G[e];
+    if (threadIdx.x == 0) info[0] = 0;
+    for (int j = 0; j < L; ++j) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double d = sG[j * L + j];
+            for (int k = 0; k < j; ++k) d -= sG[j * L + k] * sG[j * L + k];
+            if (!(d > 0.0)) {
+                info[0] = j + 1;
+                d = 1.0;
+            }
+            piv = sqrt(d);
+            sG[j * L + j] = piv;
+        }
+        __syncthreads();
+        for (int i = j + 1 + threadIdx.x; i < L; i += 256) {
+            double v = sG[i * L + j];
+            for (int k = 0; k < j; ++k) v -= sG[i * L + k] * sG[j * L + k];
+            sG[i * L + j] = v / piv;
+        }
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < L * L; e += 256) G[e] = (e % L > e / L) ? 0.0 : sG[e];   // lower triangle
+}
+
 __global__ __launch_bounds__(256) void cholesky_f64_kernel(double *__restrict__ G, int32_t L, int32_t *info) {
     __shared__ double piv;
     if (threadIdx.x == 0) info[0] = 0;
@@ -278,7 +309,10 @@ hipError_t launch_cholesky_qr2(hipStream_t st, double *U, int32_t L, int32_t N, 
                                double *G, int32_t *info) {
     for (int pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(gram_f64_kernel, dim3(L, L), dim3(256), 0, st, U, L, N, G);
-        hipLaunchKernelGGL(cholesky_f64_kernel, dim3(1), dim3(256), 0, st, G, L, info + pass);
+        if (L <= kCholLds)
+            hipLaunchKernelGGL(cholesky_lds_f64_kernel, dim3(1), dim3(256), 0, st, G, L, info + pass);
+        else
+            hipLaunchKernelGGL(cholesky_f64_kernel, dim3(1), dim3(256), 0, st, G, L, info + pass);
         hipLaunchKernelGGL(trsm_lower_f64_kernel, dim3((N + 255) / 256), dim3(256), 0, st, G, L, U, N);
         if (rows > 0)   // rows == 0: orthonormalise U alone
             hipLaunchKernelGGL(right_mul_f64_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, W, rows, L, G);
