@@ -665,6 +665,14 @@ class Whitener:
         self.log_geo = np.zeros(self.k_out)
         self.blocks = 0
 
+    def running_median(self) -> Tuple[np.ndarray, int]:
+        """Per bin, the median of the most recent c instantaneous estimates,
+        c = the largest odd count <= min(blocks seen, n_med) (reading R27),
+        and c."""
+        c = min(self.blocks, self.n_med)
+        c -= 1 - c % 2
+        return np.median(np.stack(self.recent[-c:]), axis=0), c
+
     @property
     def psd(self) -> np.ndarray:
         return np.exp(self.log_geo) * np.exp(np.euler_gamma)
@@ -680,9 +688,7 @@ class Whitener:
             P = (X.real ** 2 + X.imag ** 2) / self.w2                # instantaneous PSD
             self.recent = (self.recent + [P])[-self.n_med:]
             self.blocks += 1
-            c = min(self.blocks, self.n_med)
-            c -= 1 - c % 2                                           # largest odd count
-            med = np.median(np.stack(self.recent[-c:]), axis=0)
+            med, c = self.running_median()
             obs = np.log(med / self.beta[c])
             self.log_geo += (obs - self.log_geo) / min(self.blocks, self.n_avg)
             Y = X / np.sqrt(self.d * self.psd)

@@ -14,8 +14,12 @@ downsampling (Sec. II.B.2, readings R26-R28), CPU only.
 * timing: an impulse at input time t comes out at output time t / D
   (latency N/2 as stated), and a run of gap pushes drains the output to
   exact zeros without touching the PSD;
-* planted slips (no e^gamma, symmetric instead of periodic Hann) break a
-  pin.
+* steady state in white noise: the mean over bins and pushes of
+  log(PSD / sigma^2) is zero within 4 standard errors (about 0.0025), which
+  pins the median count c and its bias factor beta_c together: beta_5 in
+  place of beta_7 is a 0.016 bias in the log;
+* planted slips (no e^gamma, symmetric instead of periodic Hann, beta of
+  the next smaller count, a median over one estimate too few) break a pin.
 """
 import numpy as np
 import pytest
@@ -114,3 +118,63 @@ def test_planted_slip_breaks_a_pin(monkeypatch, slip):
     else:
         w.hann = np.hanning(2 * w.h)
         assert not np.allclose(w.hann[:w.h] + w.hann[w.h:], 1.0, atol=1e-6)
+
+
+STEADY_N, STEADY_Z, STEADY_PUSHES, STEADY_BURN = 1 << 16, 1 << 13, 600, 400
+
+
+def _steady_log_psd(w, sigma, seed):
+    """Mean over interior bins and over pushes STEADY_BURN.. of log(PSD /
+    sigma^2) in white noise, and its standard error from 64 groups of
+    adjacent bins (bins further apart than the Hann window's main lobe are
+    nearly independent; the groups average over hundreds of them).
+
+    Expectation: with beta_c correct, log(median of c / beta_c) averages
+    log sigma^2 - gamma for every odd c, so log PSD averages log sigma^2.
+    The first block (half zeros) biases the running average low by about
+    log(2) / n_avg; after STEADY_BURN pushes its weight has decayed by
+    (1 - 1/n_avg)^(STEADY_BURN - n_avg) < 0.006, a bias below 1e-4."""
+    x = sigma * synth.rng_for(93, synth.PURPOSE_NOISE, seed).standard_normal(STEADY_PUSHES * w.h)
+    acc = np.zeros(w.k_out - 2)
+    for i in range(STEADY_PUSHES):
+        w.push(x[i * w.h:(i + 1) * w.h])
+        if i >= STEADY_BURN:
+            acc += np.log(w.psd[1:-1] / sigma ** 2)
+    per_bin = acc / (STEADY_PUSHES - STEADY_BURN)
+    k = per_bin.shape[0] // 64 * 64
+    groups = per_bin[:k].reshape(64, -1).mean(axis=1)
+    return float(per_bin.mean()), float(groups.std(ddof=1) / np.sqrt(64))
+
+
+def _beta_of_smaller_count(w):
+    b = dict(w.beta)
+    w.beta = {c: (b[c - 2] if c >= 3 else b[c]) for c in b}
+
+
+def _median_over_one_fewer(w):
+    """Median of the most recent c - 1 estimates (an even count: NumPy
+    averages the middle two) divided by beta_c."""
+    def slipped(self):
+        c = min(self.blocks, self.n_med)
+        c -= 1 - c % 2
+        n = max(c - 1, 1)
+        return np.median(np.stack(self.recent[-n:]), axis=0), c
+    w.running_median = slipped.__get__(w)
+
+
+def test_steady_state_psd_is_unbiased():
+    w = O.Whitener(STEADY_N, STEADY_Z, d=1)
+    mean, se = _steady_log_psd(w, 2.0, 0)
+    assert abs(mean) < 4 * se + 1e-4, (mean, se)
+    assert se < 2e-3
+
+
+@pytest.mark.parametrize("slip", ["beta_of_smaller_count", "median_over_one_fewer"])
+def test_psd_bookkeeping_slip_breaks_the_steady_state_pin(slip):
+    w = O.Whitener(STEADY_N, STEADY_Z, d=1)
+    if slip == "beta_of_smaller_count":
+        _beta_of_smaller_count(w)
+    else:
+        _median_over_one_fewer(w)
+    mean, se = _steady_log_psd(w, 2.0, 0)
+    assert abs(mean) > 4 * se + 1e-4, (mean, se)
