@@ -195,8 +195,11 @@ lloid_status lloid_inspect(lloid_plan *plan, int32_t what, int32_t index, int32_
  *   L = sum over detectors, banks, real rows r and top-rate samples
  *       t in [0, n_strides F) of (rho[r,t] - target[r,t])^2
  * where rho is the plan's own output for the strain segment, filtered from
- * zero history (the streaming state is reset first and left after stride
- * n_strides).  rho is linear in every W^s and every U^s:
+ * zero history.  The plan's streaming state (history and stride count) is
+ * saved to host memory before and restored before the call returns, on
+ * success and on error, so a live plan keeps its history and the next
+ * lloid_push_stride continues where it left off.  rho is linear in every
+ * W^s and every U^s:
  *   dL/dW^s = 2 G^s Y^s^T,  dL/dU^s[l,n] = 2 sum_q (W^s^T G^s)[l,q] d^s[q - delay - (N-1) + n],
  * with Y^s the basis outputs, d^s the decimated strain and G^s the residual
  * taken down to the slice's rate by the transposed upsampling stages.

@@ -222,7 +222,10 @@ __global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict_
 }
 
 // In-place lower Cholesky factor C (G = C C^T) of an L x L SPD matrix, one
-// work group, column by column; info[0] = 0 or the failing column + 1.
+// work group, column by column.  A pivot that is not positive is replaced
+// by 1 (so the passes run on) and, if info[0] is still 0, recorded there as
+// its column + 1; info is never reset here, so a breakdown stays reported
+// until the caller clears it (launch_clear_info).
 // The same factorisation with G held in LDS, for L <= kCholLds (the column
 // updates then read LDS instead of global memory).
 constexpr int kCholLds = 88;   // 88^2 doubles = 61952 bytes of static LDS
@@ -230,14 +233,13 @@ __global__ __launch_bounds__(256) void cholesky_lds_f64_kernel(double *__restric
     __shared__ double sG[kCholLds * kCholLds];
     __shared__ double piv;
     for (int e = threadIdx.x; e < L * L; e += 256) sG[e] = G[e];
-    if (threadIdx.x == 0) info[0] = 0;
     for (int j = 0; j < L; ++j) {
         __syncthreads();
         if (threadIdx.x == 0) {
             double d = sG[j * L + j];
             for (int k = 0; k < j; ++k) d -= sG[j * L + k] * sG[j * L + k];
             if (!(d > 0.0)) {
-                info[0] = j + 1;
+                if (info[0] == 0) info[0] = j + 1;
                 d = 1.0;
             }
             piv = sqrt(d);
@@ -256,14 +258,13 @@ __global__ __launch_bounds__(256) void cholesky_lds_f64_kernel(double *__restric
 
 __global__ __launch_bounds__(256) void cholesky_f64_kernel(double *__restrict__ G, int32_t L, int32_t *info) {
     __shared__ double piv;
-    if (threadIdx.x == 0) info[0] = 0;
     for (int j = 0; j < L; ++j) {
         __syncthreads();
         if (threadIdx.x == 0) {
             double d = G[j * L + j];
             for (int k = 0; k < j; ++k) d -= G[j * L + k] * G[j * L + k];
             if (!(d > 0.0)) {
-                info[0] = j + 1;
+                if (info[0] == 0) info[0] = j + 1;
                 d = 1.0;
             }
             piv = sqrt(d);
@@ -305,6 +306,18 @@ __global__ void right_mul_f64_kernel(double *__restrict__ W, int32_t rows, int32
     }
 }
 
+__global__ void clear_info_kernel(int32_t *info, int32_t n) {
+    if ((int)threadIdx.x < n) info[threadIdx.x] = 0;
+}
+
+// A kernel rather than a memset, so that the clear can sit in a captured graph.
+hipError_t launch_clear_info(hipStream_t st, int32_t *info, int32_t n) {
+    hipLaunchKernelGGL(clear_info_kernel, dim3(1), dim3(64), 0, st, info, n);
+    return hipGetLastError();
+}
+
+// Two CholeskyQR passes; info[pass] receives the first failing column + 1
+// of that pass's factorisation if it is still 0 (cleared by the caller).
 hipError_t launch_cholesky_qr2(hipStream_t st, double *U, int32_t L, int32_t N, double *W, int32_t rows,
                                double *G, int32_t *info) {
     for (int pass = 0; pass < 2; ++pass) {
@@ -429,7 +442,9 @@ extern "C" lloid_status lloid_svd_basis(const double *H, int32_t rows, int32_t N
         return LLOID_E_NOMEM;
     }
     int32_t h[2] = {0, 0}, bad = 0;
-    hipError_t e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);   // orthonormal start
+    // cleared once: a breakdown in any pass since the start stays latched until the next check
+    hipError_t e = lloid::launch_clear_info(st, info, 2);
+    if (e == hipSuccess) e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);   // orthonormal start
     for (int it = 0; it < iters && e == hipSuccess; ++it) {
         hipLaunchKernelGGL(h_vt_kernel, dim3(rows, L), dim3(256), 0, st, H, U, N, L, T);
         hipLaunchKernelGGL(ht_t_kernel, dim3((N + 255) / 256, L, kSvdSplit), dim3(256), 0, st, H, T, rows, N, L,

@@ -1044,6 +1044,22 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
         tmp.push_back(*p);
         return LLOID_OK;
     };
+    // the caller's streaming state (history and stride counter) is saved to
+    // host memory and restored on every return, so a live plan can be
+    // differentiated without losing its history
+    std::vector<uint64_t> saved((state_bytes(P) + sizeof(uint64_t) - 1) / sizeof(uint64_t));
+    ST_OK(lloid_state_save(P, saved.data(), saved.size() * sizeof(uint64_t), stream));
+    struct Restore {
+        lloid_plan *P;
+        std::vector<uint64_t> *blob;
+        void *stream;
+        bool graph;
+        ~Restore() {
+            (void)hipDeviceSynchronize();
+            (void)lloid_state_load(P, blob->data(), blob->size() * sizeof(uint64_t), stream);
+            P->use_graph = graph;
+        }
+    } restore{P, &saved, stream, P->use_graph};
     ST_OK(lloid_reset(P, stream));
     const bool graph = P->use_graph;
     P->use_graph = false;
@@ -1362,7 +1378,8 @@ lloid_status lloid_orthonormalize(double *U, int32_t L, int32_t N, double *W, in
         return LLOID_E_NOMEM;
     }
     int32_t h[2] = {0, 0};
-    hipError_t e = launch_cholesky_qr2(st, U, L, N, W, rows, G, info);
+    hipError_t e = launch_clear_info(st, info, 2);
+    if (e == hipSuccess) e = launch_cholesky_qr2(st, U, L, N, W, rows, G, info);
     if (e == hipSuccess) e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(G);

@@ -195,3 +195,25 @@ def test_refinement_decreases_loss(lib, problem):
                                              for s, u, w in zip(bank.slices, U, W)])
     L_ref = O.loss_only(x[0], ref_bank, target, cfg, 0, T * F)
     assert abs(losses[-1] - L_ref) <= 1e-4 * L_ref
+
+
+def test_gradient_leaves_a_live_plan_history_intact(lib, problem):
+    """lloid_grad saves the plan's streaming state and restores it: a plan
+    that has filtered two strides, is differentiated on another segment and
+    then filters its third stride gives exactly the output of a plan that
+    was never differentiated."""
+    bank, x, target, T, cfg = problem
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    tg = torch.from_numpy(_target_layout(target, bank.n_templates, T)).cuda()
+    live = lib.LloidPlan([bank], F, 1, "fp32", normalize=False)
+    ref = lib.LloidPlan([bank], F, 1, "fp32", normalize=False)
+    for k in range(2):
+        live.push(xs[:, k * F:(k + 1) * F].contiguous())
+        ref.push(xs[:, k * F:(k + 1) * F].contiguous())
+    other = torch.from_numpy(synth.gaussian_strain(15, 1, T * F).astype(np.float32)).cuda()
+    live.grad(other, tg)
+    assert live.stride == 2
+    s_live, p_live = live.push(xs[:, 2 * F:3 * F].contiguous())
+    s_ref, p_ref = ref.push(xs[:, 2 * F:3 * F].contiguous())
+    torch.cuda.synchronize()
+    assert torch.equal(s_live, s_ref)
