@@ -232,6 +232,25 @@ lloid_status lloid_set_slice(lloid_plan *plan, int32_t slice, const double *U_de
  * LLOID_E_STATE if a Gram matrix is not positive definite.  Synchronises. */
 lloid_status lloid_orthonormalize(double *U_dev, int32_t L, int32_t N, double *W_dev, int32_t rows, void *stream);
 
+/* The same re-orthonormalisation for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight refinement loops, harnesses
+ * that forbid hipMalloc): no hipMalloc, hipFree or allocating library call,
+ * and no synchronisation; it only enqueues on `stream`.  Its Gram matrix
+ * and Cholesky factor live in a static device array of the library
+ * (205 056 bytes per GPU, held until the process ends), which every call on
+ * that GPU shares: calls that overlap on one GPU race and must be ordered
+ * by the caller (one stream, or events).  Results are those of
+ * lloid_orthonormalize (same kernels).
+ *   U_dev, W_dev, L, N, rows  as lloid_orthonormalize; 1 <= L <= 160
+ *   info_dev  device int32[2] or NULL: per CholeskyQR pass 0, or the first
+ *             column + 1 whose pivot was not positive (the role of
+ *             lloid_orthonormalize's LLOID_E_STATE); cleared by the call
+ * Errors: LLOID_E_ARG (NULL U or W, L < 1, N < L, rows < 1),
+ * LLOID_E_UNSUPPORTED (L > 160: the Gram matrix would not fit the static
+ * array), LLOID_E_HIP. */
+lloid_status lloid_orthonormalize_noalloc(double *U_dev, int32_t L, int32_t N, double *W_dev, int32_t rows,
+                                          int32_t *info_dev, void *stream);
+
 /* Plan options (lloid_set_option; current values via lloid_plan_query with
  * LLOID_Q_OPTION).  The three tiling options change only how the work is cut
  * into work groups, never what is computed; results stay deterministic for a

@@ -91,6 +91,8 @@ def load() -> ctypes.CDLL:
     lib.lloid_set_slice.restype = ctypes.c_int
     lib.lloid_orthonormalize.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P]
     lib.lloid_orthonormalize.restype = ctypes.c_int
+    lib.lloid_orthonormalize_noalloc.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, ctypes.c_int32, P, P]
+    lib.lloid_orthonormalize_noalloc.restype = ctypes.c_int
     lib.lloid_set_autocorrelation.argtypes = [P, P, ctypes.POINTER(ctypes.c_int32), P]
     lib.lloid_set_autocorrelation.restype = ctypes.c_int
     lib.lloid_xi2.argtypes = [P, P, P, P, P, P, P]

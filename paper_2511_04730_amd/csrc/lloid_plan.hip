@@ -10,6 +10,8 @@
 // kernels, and moves the bank to the device (FP64 normalisation there).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -300,6 +302,42 @@ lloid_status validate(const lloid_config *c, const lloid_bank *banks, int32_t n_
     return LLOID_OK;
 }
 
+}  // namespace
+
+// ---------------------------------------------- no-allocation scratch
+// Device memory of lloid_orthonormalize_noalloc: the Gram matrix / Cholesky
+// factor (at most kNoAllocMaxBasis^2 doubles) followed by the two
+// breakdown flags used when the caller passes no flag buffer.  One copy per
+// GPU, held until the process ends; every call on a GPU shares it, so calls
+// that overlap on one GPU race.  Host code must use the address from
+// hipGetSymbolAddress (per device), never the array's name.
+namespace {
+constexpr int kNoAllocMaxBasis = kMaxBasis;
+constexpr int64_t kScratchGramDoubles = (int64_t)kNoAllocMaxBasis * kNoAllocMaxBasis;
+constexpr int kMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) double scratch[kScratchGramDoubles + 32];
+
+namespace {
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// The current device's address of `scratch`, looked up once per device.
+hipError_t scratch_address(double **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 }  // namespace
 
 extern "C" {
@@ -1386,6 +1424,20 @@ lloid_status lloid_orthonormalize(double *U, int32_t L, int32_t N, double *W, in
     (void)hipFree(info);
     if (e != hipSuccess) return LLOID_E_HIP;
     return (h[0] || h[1]) ? LLOID_E_STATE : LLOID_OK;
+}
+
+lloid_status lloid_orthonormalize_noalloc(double *U, int32_t L, int32_t N, double *W, int32_t rows,
+                                          int32_t *info_dev, void *stream) {
+    if (!U || !W || L < 1 || N < L || rows < 1) return LLOID_E_ARG;
+    if (L > kNoAllocMaxBasis) return LLOID_E_UNSUPPORTED;   // the Gram matrix would not fit the scratch array
+    double *base = nullptr;
+    if (scratch_address(&base) != hipSuccess) return LLOID_E_HIP;
+    double *G = base;
+    int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(base + kScratchGramDoubles);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipError_t e = launch_clear_info(st, info, 2);
+    if (e == hipSuccess) e = launch_cholesky_qr2(st, U, L, N, W, rows, G, info);
+    return e == hipSuccess ? LLOID_OK : LLOID_E_HIP;
 }
 
 }  // extern "C"

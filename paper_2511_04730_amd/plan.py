@@ -339,6 +339,25 @@ def orthonormalize(U, W, stream=None) -> None:
             "lloid_orthonormalize")
 
 
+def orthonormalize_noalloc(U, W, info=None, stream=None) -> None:
+    """orthonormalize() through lloid_orthonormalize_noalloc: no device
+    allocation and no synchronisation (the work is only enqueued; the
+    library's static scratch array holds the Gram matrix).  `info`, if
+    given, is a cuda int32 tensor of 2 that receives per pass 0 or the
+    first failing column + 1."""
+    import torch
+    assert U.is_cuda and W.is_cuda and U.dtype == torch.float64 and W.dtype == torch.float64
+    assert U.is_contiguous() and W.is_contiguous() and W.shape[1] == U.shape[0]
+    if info is not None:
+        assert info.is_cuda and info.dtype == torch.int32 and info.numel() >= 2
+    lib = L.load()
+    L.check(lib.lloid_orthonormalize_noalloc(ctypes.c_void_p(U.data_ptr()), U.shape[0], U.shape[1],
+                                             ctypes.c_void_p(W.data_ptr()), W.shape[0],
+                                             ctypes.c_void_p(info.data_ptr() if info is not None else None),
+                                             _stream_handle(stream)),
+            "lloid_orthonormalize_noalloc")
+
+
 class Whitener:
     """PSD estimation and whitening with frequency-domain downsampling for
     n_detectors streams (lloid_whitener_*): push() takes H = block/2 - pad

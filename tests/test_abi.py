@@ -104,3 +104,16 @@ def test_latency_error_matches_oracle(L):
                           [(1024, 0.0, 128, 8), (256, need / 256, 200, 8)], seed=[1, 1, 0])
     assert O.latency_violations(ok, 1024) == []
     assert _create(L, [ok]) not in (-1, -2, -3)
+
+
+def test_noalloc_orthonormalize_host_checks(L):
+    """The no-allocation re-orthonormalisation rejects bad sizes on the host
+    before any device work: NULL buffers and L < 1 with LLOID_E_ARG, a basis
+    larger than its static Gram array (L > 160) with LLOID_E_UNSUPPORTED."""
+    lib = L.load()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: rejected first
+    assert lib.lloid_orthonormalize_noalloc(None, 8, 100, fake, 10, None, None) == -1
+    assert lib.lloid_orthonormalize_noalloc(fake, 8, 100, None, 10, None, None) == -1
+    assert lib.lloid_orthonormalize_noalloc(fake, 0, 100, fake, 10, None, None) == -1
+    assert lib.lloid_orthonormalize_noalloc(fake, 8, 7, fake, 10, None, None) == -1
+    assert lib.lloid_orthonormalize_noalloc(fake, 161, 400, fake, 10, None, None) == -7
