@@ -365,13 +365,13 @@ def main() -> int:
             for kv in args.tiling.split(","):
                 k, v = kv.split("=")
                 plan.set_option(k.strip(), int(v))
-            tiling[precision] = {k: plan.option(k) for k in ("corr_cols", "corr_split", "corr_group", "mix_group")}
+            tiling[precision] = {k: plan.option(k) for k in ("corr_cols", "corr_split", "corr_group", "mix_group", "mix_tblock")}
         elif args.autotune:
             from paper_2511_04730_amd.autotune import autotune
             best = autotune(plan, strides[:4], write_series=write, log=log)
-            tiling[precision] = {k: best[k] for k in ("corr_cols", "corr_split", "corr_group", "mix_group")}
+            tiling[precision] = {k: best[k] for k in ("corr_cols", "corr_split", "corr_group", "mix_group", "mix_tblock")}
         else:
-            tiling[precision] = {k: plan.option(k) for k in ("corr_cols", "corr_split", "corr_group", "mix_group")}
+            tiling[precision] = {k: plan.option(k) for k in ("corr_cols", "corr_split", "corr_group", "mix_group", "mix_tblock")}
         if args.graph and not profile:
             plan.set_graph(True)
         ms, prof = timed(plan, strides, warmup, steps, write, profile)

@@ -268,6 +268,11 @@ lloid_status lloid_orthonormalize_noalloc(double *U_dev, int32_t L, int32_t N, d
  *                    (0..64; 0 = dispatch order; default 16).
  *   LLOID_OPT_MIX_GROUP   consecutive mixing items kept on one XCD
  *                    (0..256; 0 = dispatch order; default 32).
+ *   LLOID_OPT_MIX_TBLOCK  time tiles per block of the mixing item order
+ *                    (1..64; default 1): per bank and detector the items
+ *                    run in blocks of this many 256-sample time tiles, row
+ *                    tiles inner within a block, so that the items an XCD
+ *                    runs together share W~ rows and basis-output windows.
  *   LLOID_OPT_GRAPH  1: lloid_push_stride copies the strain into a
  *                    plan-owned staging buffer on the call's stream and then
  *                    replays one captured HIP graph of the stride's kernels
@@ -285,7 +290,8 @@ typedef enum {
     LLOID_OPT_CORR_SPLIT = 1,
     LLOID_OPT_CORR_GROUP = 2,
     LLOID_OPT_MIX_GROUP = 3,
-    LLOID_OPT_CORR_COLS = 4
+    LLOID_OPT_CORR_COLS = 4,
+    LLOID_OPT_MIX_TBLOCK = 5
 } lloid_option;
 lloid_status lloid_set_option(lloid_plan *plan, int32_t option, int64_t value);
 

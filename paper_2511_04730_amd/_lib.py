@@ -20,7 +20,7 @@ Q_N_BANKS, Q_TOTAL_TEMPLATES, Q_SERIES_FLOATS, Q_N_PEAKS = 0, 1, 2, 3
 Q_BANK_SERIES_OFFSET, Q_BANK_PEAK_OFFSET, Q_BANK_TEMPLATES, Q_STRIDE = 4, 5, 6, 7
 Q_N_SLICES, Q_SLICE_LOOKAHEAD, Q_FLOPS_PER_STRIDE, Q_DEVICE_BYTES = 8, 9, 10, 11
 Q_OPTION = 12
-OPTIONS = {"graph": 0, "corr_split": 1, "corr_group": 2, "mix_group": 3, "corr_cols": 4}
+OPTIONS = {"graph": 0, "corr_split": 1, "corr_group": 2, "mix_group": 3, "corr_cols": 4, "mix_tblock": 5}
 INSPECT_DOWNSAMPLED, INSPECT_BASIS_OUT = 0, 1
 KERNEL_NAMES = ["ingest", "down", "corr", "reduce", "mix", "peaks", "xi2", "triggers", "coinc"]
 

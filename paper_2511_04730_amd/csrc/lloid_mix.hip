@@ -54,6 +54,8 @@
 
 namespace lloid {
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 // The four waves tile the work group's kMixTM x kMixTN block as kWR x kWC:
 // wave (wr, wc) owns rows wr kMixTM/kWR .. + kMixTM/kWR (kRB 16-row
 // blocks) and the column blocks cb = wc, wc + kWC, ... (kCB of them).
@@ -511,7 +513,11 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     const int c = cb * 16 + li;
                     if (c >= n) continue;
                     const float re = acc[i][m][2 * h], im = acc[i][m][2 * h + 1];
-                    if (orow && live) orow[(int64_t)(8 * m + h) * F + cb * 16] = make_float2(re, im);
+                    // streamed past the caches: the series is never re-read by this
+                    // launch and would otherwise evict W~ and the basis outputs
+                    if (orow && live)
+                        __builtin_nontemporal_store(f32x2{re, im},
+                                                    reinterpret_cast<f32x2 *>(orow + (int64_t)(8 * m + h) * F + cb * 16));
                     const float p2 = re * re + im * im;
                     if (better(p2, it.t0 + c, b.p2, b.idx)) b = PeakCand{p2, it.t0 + c, re, im};
                 }

@@ -137,6 +137,8 @@ struct lloid_plan {
     int corr_cols = kCorrTQ;       // output columns per correlation work item
     int corr_group = 16;           // consecutive correlation items per XCD
     int mix_group = 32;            // consecutive mixing items per XCD
+    int mix_tblock = 1;            // time tiles per block of the mixing item order
+    std::vector<MixItem> h_mix;    // mixing items in bank, detector, time tile, row tile order
 
     // per-kernel event timing (lloid_profile_*)
     bool profiling = false;
@@ -337,6 +339,27 @@ hipError_t scratch_address(double **out) {
     }
     *out = g_scratch_ptr[dev];
     return hipSuccess;
+}
+}  // namespace
+
+namespace {
+// The mixing items of one bank and detector in blocks of `tblock` time
+// tiles: row tiles inner within a block, so that a group of consecutive
+// items (dealt to one XCD) covers a few row tiles x a few time tiles and
+// shares both the W~ rows and the basis-output windows in that XCD's L2.
+// The input is in bank, detector, time tile, row tile order.
+std::vector<MixItem> mix_item_order(const std::vector<MixItem> &items, int tblock) {
+    if (tblock <= 1) return items;
+    std::vector<MixItem> out(items);
+    std::stable_sort(out.begin(), out.end(), [&](const MixItem &a, const MixItem &b) {
+        if (a.bank != b.bank) return a.bank < b.bank;
+        if (a.det != b.det) return a.det < b.det;
+        const int ba = a.t0 / (tblock * kMixTN), bb = b.t0 / (tblock * kMixTN);
+        if (ba != bb) return ba < bb;
+        if (a.r0 != b.r0) return a.r0 < b.r0;
+        return a.t0 < b.t0;
+    });
+    return out;
 }
 }  // namespace
 
@@ -712,7 +735,8 @@ lloid_status lloid_plan_create(const lloid_config *config, const lloid_bank *ban
         P->n_peakitems = (int)pk.size();
         ST_OK(upload(P, &P->d_mbanks, mb, st));
         ST_OK(upload(P, &P->d_mslices, ms, st));
-        ST_OK(upload(P, &P->d_mix, items, st));
+        P->h_mix = items;
+        ST_OK(upload(P, &P->d_mix, mix_item_order(items, 1), st));
         ST_OK(upload(P, &P->d_peakitems, pk, st));
         ST_OK(P->alloc(&P->d_partials, (size_t)std::max<int64_t>(part_off, 1)));
     }
@@ -750,6 +774,7 @@ lloid_status lloid_plan_query(const lloid_plan *P, int32_t what, int32_t index, 
             case LLOID_OPT_CORR_SPLIT: *value = P->ksplit; return LLOID_OK;
             case LLOID_OPT_CORR_GROUP: *value = P->corr_group; return LLOID_OK;
             case LLOID_OPT_MIX_GROUP: *value = P->mix_group; return LLOID_OK;
+            case LLOID_OPT_MIX_TBLOCK: *value = P->mix_tblock; return LLOID_OK;
             case LLOID_OPT_CORR_COLS: *value = P->corr_cols; return LLOID_OK;
             default: return LLOID_E_ARG;
         }
@@ -827,6 +852,9 @@ lloid_status lloid_set_option(lloid_plan *P, int32_t option, int64_t value) {
         case LLOID_OPT_MIX_GROUP:
             if (value < 0 || value > 256) return LLOID_E_ARG;
             break;
+        case LLOID_OPT_MIX_TBLOCK:
+            if (value < 1 || value > 64) return LLOID_E_ARG;
+            break;
         default:
             return LLOID_E_ARG;
     }
@@ -848,6 +876,11 @@ lloid_status lloid_set_option(lloid_plan *P, int32_t option, int64_t value) {
     }
     if (option == LLOID_OPT_CORR_GROUP) P->corr_group = (int)value;
     if (option == LLOID_OPT_MIX_GROUP) P->mix_group = (int)value;
+    if (option == LLOID_OPT_MIX_TBLOCK && P->mix_tblock != (int)value) {
+        P->mix_tblock = (int)value;
+        const std::vector<MixItem> order = mix_item_order(P->h_mix, P->mix_tblock);
+        HIP_OK(hipMemcpy(P->d_mix, order.data(), sizeof(MixItem) * order.size(), hipMemcpyHostToDevice));
+    }
     return LLOID_OK;
 }
 

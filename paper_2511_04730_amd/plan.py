@@ -80,7 +80,7 @@ class LloidPlan:
         self.set_option("graph", 1 if enable else 0)
 
     def set_option(self, name: str, value: int) -> None:
-        """lloid_set_option by name: graph, corr_split, corr_cols, corr_group, mix_group."""
+        """lloid_set_option by name: graph, corr_split, corr_cols, corr_group, mix_group, mix_tblock."""
         L.check(self.lib.lloid_set_option(self.handle, L.OPTIONS[name], int(value)), "lloid_set_option")
 
     def option(self, name: str) -> int:

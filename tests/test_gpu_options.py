@@ -44,13 +44,14 @@ def test_grouping_and_columns_are_bit_exact(plan_cls, precision):
     ref.set_option("corr_group", 0)
     ref.set_option("mix_group", 0)
     z0, p0 = run_gpu(ref, x, 0, 4)
-    for cg, mg, cols in [(16, 32, 256), (3, 5, 64), (64, 256, 192), (1, 1, 128)]:
+    for cg, mg, cols, tb in [(16, 32, 256, 1), (3, 5, 64, 3), (64, 256, 192, 16), (1, 1, 128, 64)]:
         plan = plan_cls(banks, F, 2, precision)
         plan.set_option("corr_group", cg)
         plan.set_option("mix_group", mg)
         plan.set_option("corr_cols", cols)
+        plan.set_option("mix_tblock", tb)
         assert plan.option("corr_group") == cg and plan.option("mix_group") == mg
-        assert plan.option("corr_cols") == cols
+        assert plan.option("corr_cols") == cols and plan.option("mix_tblock") == tb
         z, p = run_gpu(plan, x, 0, 4)
         for b in range(len(banks)):
             assert np.array_equal(z[b], z0[b]), f"groups {cg},{mg} bank {b}"
@@ -72,6 +73,7 @@ def test_grouping_change_inside_graph_mode(plan_cls):
         if k == 2:
             plan.set_option("mix_group", 7)
             plan.set_option("corr_group", 0)
+            plan.set_option("mix_tblock", 4)
         plan.push(xs[:, k * F:(k + 1) * F].contiguous(), series=series, peaks=peaks)
         out.append([plan.bank_view(series, b).cpu().numpy().astype(np.complex128) for b in range(2)])
     torch.cuda.synchronize()
@@ -120,7 +122,7 @@ def test_option_values_are_checked(plan_cls):
     plan = plan_cls(_ragged_banks()[:1], F, 1, "fp32")
     for name, bad in [("corr_split", 0), ("corr_split", 100), ("corr_split", 65600), ("corr_group", -1),
                       ("corr_group", 65), ("mix_group", 257), ("graph", 2), ("corr_cols", 0),
-                      ("corr_cols", 100), ("corr_cols", 576)]:
+                      ("corr_cols", 100), ("corr_cols", 576), ("mix_tblock", 0), ("mix_tblock", 65)]:
         with pytest.raises(LloidError):
             plan.set_option(name, bad)
     opts = plan.options()
