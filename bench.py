@@ -115,6 +115,65 @@ def kernel_flops(w) -> dict:
     return {"corr": corr * w.n_detectors, "mix": mix * w.n_detectors}
 
 
+ELT_U = {"fp32": 4, "bf16x3": 4, "fp16": 2, "fp8_bf16": 1}    # bytes per basis value (hi + lo where split)
+ELT_W = {"fp32": 4, "bf16x3": 4, "fp16": 2, "fp8_bf16": 4}    # bytes per mixing value (FP8 form mixes in BF16x3)
+MIX_TN = 256                                                   # top-rate samples per mixing time tile
+
+
+def kernel_bytes(w, precision: str, write_series: bool = True) -> dict:
+    """Algorithmic HBM bytes per launch of the stride's kernels (all banks and
+    detectors): what each kernel must read or write at least once.
+      down   the stride's strain read, every decimated stream written (4 B)
+      corr   every basis read once, every new basis output written (4 B:
+             FP32 or the hi + lo halves)
+      mix    every mixing row read once, every detector's basis-output window
+             read once, the SNR series written (8 B per SNR-sample), one
+             16-B trigger candidate per template, detector and time tile
+      peaks  the candidates read, one 20-B trigger per template and detector"""
+    nd, F = w.n_detectors, w.sample_rate
+    ntt = F // MIX_TN
+    out = {"down": 0.0, "corr": 0.0, "mix": 0.0, "peaks": 0.0}
+    rates = set()
+    for bank in w.banks:
+        M = bank.n_templates
+        for s in bank.slices:
+            rates.add(s.rate)
+            y = 4.0 * s.n_basis * s.rate * nd
+            out["corr"] += ELT_U[precision] * s.n_basis * s.n_taps + y
+            out["mix"] += ELT_W[precision] * 2 * M * s.n_basis + y
+        out["mix"] += nd * M * ((8.0 * F if write_series else 0.0) + 16.0 * ntt)
+        out["peaks"] += nd * M * (16.0 * ntt + 20.0)
+    out["down"] = nd * 4.0 * (F + sum(r for r in rates if r < F))
+    return out
+
+
+def roof(flops: float, nbytes: float, ms: float, mfma_peak_tflops: float) -> dict:
+    """Both roofs of one kernel: the fraction of the MFMA peak its
+    algorithmic flops reach and of the HBM peak its algorithmic bytes reach
+    in `ms`; `bound` is the roof with the larger ideal time, `frac` its
+    fraction."""
+    t_mfma = flops / (mfma_peak_tflops * 1e12) if flops else 0.0
+    t_hbm = nbytes / (HBM_GBS * 1e9)
+    sec = ms / 1e3
+    r = {"ms": ms, "flops": flops, "bytes": nbytes,
+         "mfma_tflops": flops / sec / 1e12, "mfma_peak": mfma_peak_tflops, "mfma_frac": t_mfma / sec,
+         "hbm_gbs": nbytes / sec / 1e9, "hbm_peak": HBM_GBS, "hbm_frac": t_hbm / sec}
+    r["bound"] = "mfma" if t_mfma > t_hbm else "hbm"
+    r["frac"] = max(t_mfma, t_hbm) / sec
+    return r
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def timed(plan, strides, warmup: int, steps: int, write: bool, profile: bool):
     import torch
     series = plan.new_series() if write else None
@@ -268,39 +327,108 @@ def svd_measure(reps: int = 3, rows: int = 2048, n: int = 1024, rank: int = 40, 
                          "frac": flops / (ms / 1e3) / 1e12 / 78.6}}
 
 
-def parity_and_baseline(plan, w, x, strides, k: int, seconds: float):
-    """Oracle (FP64, host cores) on detector 0 for stride k of as many banks
-    as fit in `seconds`; GPU series of the same banks and stride from a fresh
-    run; returns (cpu_baseline dict, max SNR error, banks sampled)."""
+def gpu_stride_series(plan, strides, k: int):
+    """The plan's series of stride k (fresh run of strides 0..k), per bank
+    and detector 0, as complex128 host arrays."""
     import numpy as np
     import torch
-    from oracle import lloid as O
-    F = w.sample_rate
     plan.reset()
     series = plan.new_series()
     peaks = plan.new_peaks()
     for i in range(k + 1):
-        plan.push(strides[i], series=series, peaks=peaks)
+        plan.push(strides[i], series=series, peaks=peaks, write_series=(i == k))
     torch.cuda.synchronize()
+    return series
+
+
+def parity_and_baseline(plan, w, x, strides, k: int, seconds: float, repeats: int = 5):
+    """The oracle (FP64 NumPy on the host cores) on detector 0 for stride k
+    of the first banks, as many as fill about seconds / (repeats + 2) per
+    repeat; `repeats` timed repeats with all host threads (median) and the
+    first bank alone with a single BLAS thread; the SNR error of the GPU series of the same
+    banks and stride against it.  Returns (cpu_baseline dict, max SNR error,
+    banks sampled)."""
+    import numpy as np
+    from oracle import lloid as O
+    from threadpoolctl import threadpool_limits
+    F = w.sample_rate
+    series = gpu_stride_series(plan, strides, k)
     cfg = O.OracleConfig(F)
     cores = len(os.sched_getaffinity(0))
-    err, done_b, samples, t0 = 0.0, 0, 0, time.perf_counter()
     xd = x[0, :(k + 1) * F]
+    # first pass: choose the sample, check parity
+    err, nb, samples, t0 = 0.0, 0, 0, time.perf_counter()
+    budget = seconds / (repeats + 2)
+    zs = []
     for b, bank in enumerate(w.banks):
-        ts = time.perf_counter()
         z, _ = O.lloid_filter(xd, bank, cfg, n_strides=1, first_stride=k)
+        zs.append(z)
         samples += bank.n_templates * F
-        done_b += 1
+        nb += 1
         zg = plan.bank_view(series, b)[0].cpu().numpy().astype(np.complex128)
         err = max(err, float((np.abs(zg - z) / np.maximum(np.abs(z), 4.0)).max()))
-        if time.perf_counter() - t0 >= seconds:
+        if time.perf_counter() - t0 >= budget:
             break
-    el = time.perf_counter() - t0
-    base = {"value": samples / el, "unit": "SNR-samples/s", "cores": cores, "kind": "oracle",
-            "sample": f"stride {k} of detector 0 for the first {done_b} of {len(w.banks)} banks "
-                      f"({samples} SNR-samples), float64 NumPy, BLAS threads = {cores}"}
-    del series, peaks
-    return base, err, done_b
+    del series
+
+    def one_pass(n):
+        ts = time.perf_counter()
+        for bank in w.banks[:n]:
+            O.lloid_filter(xd, bank, cfg, n_strides=1, first_stride=k)
+        return time.perf_counter() - ts
+
+    times = [one_pass(nb) for _ in range(repeats)]
+    with threadpool_limits(1):
+        t1 = one_pass(1)
+    med = float(np.median(times))
+    base = {"value": samples / med, "unit": "SNR-samples/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "repeats": repeats, "seconds_per_repeat": times,
+            "value_1thread": w.banks[0].n_templates * F / t1,
+            "sample": f"stride {k} of detector 0 for the first {nb} of {len(w.banks)} banks "
+                      f"({samples} SNR-samples), float64 NumPy, BLAS threads = {cores} (median of {repeats} "
+                      f"repeats); value_1thread: the first bank with one BLAS thread"}
+    return base, err, zs
+
+
+def leg_error(plan, strides, k: int, zs) -> float:
+    """SNR error of another plan's stride-k series against the oracle series
+    `zs` of the first len(zs) banks (detector 0)."""
+    import numpy as np
+    series = gpu_stride_series(plan, strides, k)
+    err = 0.0
+    for b, z in enumerate(zs):
+        zg = plan.bank_view(series, b)[0].cpu().numpy().astype(np.complex128)
+        err = max(err, float((np.abs(zg - z) / np.maximum(np.abs(z), 4.0)).max()))
+    return err
+
+
+def bank_loop(w, strides, warmup: int, steps: int, precision: str = "fp32"):
+    """The unstacked baseline: one plan per bank, each filtering the stride
+    with its own launches (no graph), banks in a host loop per stride.
+    Returns ms for `steps` strides."""
+    import torch
+    from paper_2511_04730_amd import LloidPlan
+    F, ND = w.sample_rate, w.n_detectors
+    plans = [LloidPlan([b], F, ND, precision) for b in w.banks]
+    outs = [(p.new_series(), p.new_peaks()) for p in plans]
+    n = len(strides)
+    for k in range(warmup):
+        for p, (se, pk) in zip(plans, outs):
+            p.push(strides[k % n], series=se, peaks=pk)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for k in range(warmup, warmup + steps):
+        for p, (se, pk) in zip(plans, outs):
+            p.push(strides[k % n], series=se, peaks=pk)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    for p in plans:
+        p.close()
+    del outs
+    return ms
 
 
 def main() -> int:
@@ -310,9 +438,12 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="batched", choices=["batched", "realistic", "plain", "largest"])
     ap.add_argument("--precision", default="bf16x3", choices=sorted(PEAK_TFLOPS))
-    ap.add_argument("--compare", default="fp32", help="also time this precision ('' to skip)")
+    ap.add_argument("--compare", default="fp32,fp16", help="also time these precisions, comma-separated ('' to skip)")
     ap.add_argument("--graph", type=int, default=1, help="replay one HIP graph per stride")
-    ap.add_argument("--peaks-only", action="store_true")
+    ap.add_argument("--peaks-only", action="store_true", help="time without writing the series")
+    ap.add_argument("--peaks-only-leg", type=int, default=1, help="also time the peaks-only mode")
+    ap.add_argument("--loop-leg", type=int, default=-1,
+                    help="also time one FP32 plan per bank in a host loop (-1: batched workload only)")
     ap.add_argument("--autotune", type=int, default=1, help="tune the tiling options before timing")
     ap.add_argument("--tiling", default="", help="fixed tiling instead of autotuning, "
                                                  "e.g. corr_split=8192,corr_group=32,mix_group=16")
@@ -381,13 +512,40 @@ def main() -> int:
     log(f"{args.precision}: {steps} strides in {ms:.2f} ms")
     samples = w.n_templates * F * ND * steps
     value = samples / (ms / 1e3)
+    # the same K strides timed four more times: median of five
+    reps = [ms] + [timed(plan, strides, 0, steps, write, False)[0] for _ in range(4)]
+    ms_med = float(np.median(reps))
     # per-kernel HIP-event timing over a second timed region (direct launches)
     _, prof = timed(plan, strides, 0, min(steps, 16), write, True)
-    dom = max(("corr", "mix"), key=lambda k: prof[k][0])
-    avg_ms = prof[dom][0] / max(prof[dom][1], 1)
-    achieved = kf[dom] / (avg_ms / 1e3) / 1e12
-    peak = kernel_peak(args.precision, dom)
     kernel_ms = {k: round(v[0] / v[1], 5) for k, v in prof.items() if v[1] > 0}   # the stride's kernels
+    kb = kernel_bytes(w, args.precision, write)
+    roofs = {}
+    for k in ("down", "corr", "mix", "peaks"):
+        if k in kernel_ms:
+            roofs[k] = roof(kf.get(k, 0.0), kb[k], kernel_ms[k], kernel_peak(args.precision, k))
+    dom = max(("corr", "mix"), key=lambda k: kernel_ms.get(k, 0.0))
+    d = roofs[dom]
+    if d["bound"] == "hbm":
+        top_roof = {"bound": "hbm", "kernel": dom, "achieved": d["hbm_gbs"], "peak": HBM_GBS, "unit": "GB/s",
+                    "frac": d["hbm_frac"], "bytes_per_launch": d["bytes"]}
+    else:
+        top_roof = {"bound": "mfma", "kernel": dom, "achieved": d["mfma_tflops"], "peak": d["mfma_peak"],
+                    "unit": "TFLOP/s", "frac": d["mfma_frac"], "flops_per_launch": d["flops"]}
+    top_roof["traffic"] = measured_traffic(dom, args.workload, args.precision)
+    top_roof["mfma_frac"], top_roof["hbm_frac"] = d["mfma_frac"], d["hbm_frac"]
+    # the whole stride against its own bound: all kernels' flops at the MFMA
+    # peak of their arithmetic, or all their bytes at the HBM peak
+    t_f = sum(kf[k] / (kernel_peak(args.precision, k) * 1e12) for k in ("corr", "mix"))
+    t_b = sum(kb.values()) / (HBM_GBS * 1e9)
+    stride_roof = {"ms": ms / steps, "mfma_ms": t_f * 1e3, "hbm_ms": t_b * 1e3,
+                   "bound": "mfma" if t_f > t_b else "hbm", "frac": max(t_f, t_b) / (ms / steps / 1e3)}
+
+    # peaks-only mode (no series written): the same plan, K strides
+    peaks_only = None
+    if write and args.peaks_only_leg:
+        pms, _ = timed(plan, strides, 0, steps, False, False)
+        peaks_only = {"ms_per_step": pms / steps, "value": samples / (pms / 1e3)}
+        log(f"peaks only: {pms / steps:.3f} ms per stride")
 
     xi2 = coinc = None
     if args.xi2 == 1 or (args.xi2 == -1 and args.workload != "largest"):
@@ -420,26 +578,35 @@ def main() -> int:
         svd = svd_measure()
         log(f"svd bank construction: {svd['ms']:.2f} ms per slice")
 
-    base = err = None
+    base = err = zs = None
     if not args.no_cpu_baseline:
-        base, err, nb = parity_and_baseline(plan, w, x, strides, k_par, args.cpu_seconds)
-        log(f"oracle sample: {nb} banks, SNR err {err:.3e}")
+        base, err, zs = parity_and_baseline(plan, w, x, strides, k_par, args.cpu_seconds)
+        log(f"oracle sample: {len(zs)} banks, SNR err {err:.3e}")
     flops_per_stride = plan.flops_per_stride
     plan.close()
     del plan
     torch.cuda.synchronize()
 
-    compare = None
-    if args.compare and args.compare != args.precision:
-        cplan, cms, _ = run(args.compare, profile=False)
-        cval = samples / (cms / 1e3)
-        cerr = None
-        if not args.no_cpu_baseline:
-            _, cerr, _ = parity_and_baseline(cplan, w, x, strides, k_par, min(args.cpu_seconds, 5.0))
-        compare = {"precision": args.compare, "value": cval, "ms_per_step": cms / steps,
-                   "snr_err": cerr, "speedup": value / cval, "tiling": tiling.get(args.compare)}
-        log(f"{args.compare}: {steps} strides in {cms:.2f} ms")
+    # other forms of the same batched launch (the plain FP32 path; FP16)
+    compare = []
+    for cp in [c for c in args.compare.split(",") if c and c != args.precision]:
+        cplan, cms, _ = run(cp, profile=False)
+        cerr = leg_error(cplan, strides, k_par, zs) if zs is not None else None
+        compare.append({"precision": cp, "value": samples / (cms / 1e3), "ms_per_step": cms / steps,
+                        "snr_err": cerr, "headline_speedup": value / (samples / (cms / 1e3)),
+                        "tiling": tiling.get(cp)})
+        log(f"{cp}: {steps} strides in {cms:.2f} ms, SNR err {cerr}")
         cplan.close()
+        del cplan
+    # the unstacked baseline: one plain FP32 plan per bank, launched bank by bank
+    loop = None
+    if args.loop_leg == 1 or (args.loop_leg == -1 and args.workload == "batched"):
+        lms = bank_loop(w, strides, warmup, steps)
+        lval = samples / (lms / 1e3)
+        loop = {"precision": "fp32", "form": "one plan per bank, launched in a host loop, no graph",
+                "value": lval, "ms_per_step": lms / steps, "headline_speedup": value / lval,
+                "speedups": {c["precision"]: c["value"] / lval for c in compare}}
+        log(f"per-bank FP32 loop: {lms / steps:.3f} ms per stride")
 
     out = {
         "metric": METRIC, "value": value, "unit": "SNR-samples/s", "n_gpus": 1, "steps": steps,
@@ -449,8 +616,11 @@ def main() -> int:
                    "rates_hz": sorted({s.rate for b in w.banks for s in b.slices}, reverse=True),
                    "precision": args.precision, "series_written": write, "graph": bool(args.graph),
                    "stride_s": 1, "flops_per_stride": flops_per_stride, "tiling": tiling.get(args.precision)},
-        "roofline": {"bound": "mfma", "kernel": dom, "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": measured_traffic(dom, args.workload, args.precision)},
+        "roofline": top_roof,
+        "stride_roofline": stride_roof,
+        "kernel_roofline": roofs,
+        "ms_per_step_median5": ms_med / steps,
+        "peaks_only": peaks_only,
         "kernel_ms": kernel_ms,
         "xi2": xi2,
         "coincidence": coinc,
@@ -458,6 +628,7 @@ def main() -> int:
         "svd_bank": svd,
         "snr_err": err,
         "compare": compare,
+        "baseline_loop": loop,
         "cpu_baseline": base,
     }
     print(json.dumps(out), flush=True)

@@ -290,6 +290,31 @@ def slice_lookahead_s(rates_desc: Sequence[int], r: int, n_down: int = 32, n_up:
     return n_down / rates_desc[r] + sum(n_up / rates_desc[j] for j in range(1, r + 1))
 
 
+def subbank_shape(g: np.random.Generator, top_rate: int, n_rates_range: Tuple[int, int],
+                  templates_range: Tuple[int, int], duration_range: Tuple[float, float]):
+    """The first draws of a sub-bank: templates M, rate count R, the rates,
+    the per-rate lower bounds of the slice boundaries and the duration T."""
+    M = int(g.integers(templates_range[0], templates_range[1] + 1))
+    R = int(g.integers(n_rates_range[0], n_rates_range[1] + 1))
+    rates = [top_rate >> r for r in range(R)]
+    tmin = [0.0] + [np.ceil(1.5 * slice_lookahead_s(rates, r) * rates[r]) / rates[r] for r in range(1, R)]
+    lo = max(duration_range[0], 2.0 * tmin[R - 1])
+    T = float(np.exp(g.uniform(np.log(lo), np.log(max(lo, duration_range[1])))))
+    return M, R, rates, tmin, T
+
+
+def subbank_boundaries(rates: Sequence[int], tmin: Sequence[float], T: float) -> List[float]:
+    """Slice boundaries tau_0 = 0 < tau_1 < ... < tau_R = T in seconds, each
+    on its rate's sample grid."""
+    R = len(rates)
+    taus = [0.0]
+    for r in range(1, R):
+        t = max(tmin[r], T * 4.0 ** (-(R - r)))
+        taus.append(np.round(t * rates[r]) / rates[r])
+    taus.append(np.round(T * rates[R - 1]) / rates[R - 1])
+    return taus
+
+
 def random_subbank(g: np.random.Generator, top_rate: int, n_rates_range: Tuple[int, int],
                    templates_range: Tuple[int, int], duration_range: Tuple[float, float],
                    basis_range: Tuple[int, int], dtype=np.float64) -> Bank:
@@ -301,17 +326,8 @@ def random_subbank(g: np.random.Generator, top_rate: int, n_rates_range: Tuple[i
     a Gaussian QR; W rows are Gaussian x exp(-3 l / L), rows jointly
     normalised over slices.
     """
-    M = int(g.integers(templates_range[0], templates_range[1] + 1))
-    R = int(g.integers(n_rates_range[0], n_rates_range[1] + 1))
-    rates = [top_rate >> r for r in range(R)]
-    tmin = [0.0] + [np.ceil(1.5 * slice_lookahead_s(rates, r) * rates[r]) / rates[r] for r in range(1, R)]
-    lo = max(duration_range[0], 2.0 * tmin[R - 1])
-    T = float(np.exp(g.uniform(np.log(lo), np.log(max(lo, duration_range[1])))))
-    taus = [0.0]
-    for r in range(1, R):
-        t = max(tmin[r], T * 4.0 ** (-(R - r)))
-        taus.append(np.round(t * rates[r]) / rates[r])
-    taus.append(np.round(T * rates[R - 1]) / rates[R - 1])
+    M, R, rates, tmin, T = subbank_shape(g, top_rate, n_rates_range, templates_range, duration_range)
+    taus = subbank_boundaries(rates, tmin, T)
     slices = []
     rows = []
     for r in range(R):
@@ -430,12 +446,46 @@ def config4(duration_s: int = 64) -> Workload:
 
 def batched_banks(config: int, n_banks: int, n_rates_range, duration_range,
                   dtype=np.float64, progress=None) -> List[Bank]:
+    """Sub-banks drawn one after another from one generator (the batched
+    workload's banks)."""
     g = rng_for(config, PURPOSE_STRUCT)
     banks = []
     for i in range(n_banks):
         banks.append(random_subbank(g, 4096, n_rates_range, (200, 1000), duration_range, (20, 150), dtype))
         if progress is not None and (i + 1) % 100 == 0:
             progress(f"generated {i + 1} of {n_banks} banks")
+    return banks
+
+
+# the largest workload draws every sub-bank from its own generator, so that a
+# test can build any subset of its banks without generating the rest
+C5_RATES, C5_DURATION = (3, 6), (0.5, 128.0)
+
+
+def _c5_rng(i: int) -> np.random.Generator:
+    return rng_for(5, PURPOSE_STRUCT, i + 1)
+
+
+def config5_shapes(n_banks: int = 800) -> List[Tuple[int, int, float, int]]:
+    """(templates, rates, duration in s, longest slice in taps) of every
+    sub-bank of the largest workload, from the first draws of its generator
+    only."""
+    out = []
+    for i in range(n_banks):
+        M, R, rates, tmin, T = subbank_shape(_c5_rng(i), 4096, C5_RATES, (200, 1000), C5_DURATION)
+        taus = subbank_boundaries(rates, tmin, T)
+        nmax = max(int(round((taus[r + 1] - taus[r]) * rates[r])) for r in range(R))
+        out.append((M, R, T, nmax))
+    return out
+
+
+def config5_banks(indices: Sequence[int], dtype=np.float64, progress=None) -> List[Bank]:
+    """The largest workload's sub-banks with the given indices."""
+    banks = []
+    for n, i in enumerate(indices):
+        banks.append(random_subbank(_c5_rng(int(i)), 4096, C5_RATES, (200, 1000), C5_DURATION, (20, 150), dtype))
+        if progress is not None and (n + 1) % 100 == 0:
+            progress(f"generated {n + 1} of {len(indices)} banks")
     return banks
 
 
@@ -450,7 +500,7 @@ def config5(n_banks: int = 800, duration_s: int = 1024, dtype=np.float64, progre
     """Largest single-GPU share: 2 detectors, 1024 s at 4096 Hz, 800 uneven
     sub-banks (up to 6 rates, lowest 128 Hz, filters up to 128 s)."""
     return Workload("batched-800banks-2det-4096Hz", 5, 4096, 2, duration_s,
-                    batched_banks(5, n_banks, (3, 6), (0.5, 128.0), dtype, progress))
+                    config5_banks(range(n_banks), dtype, progress))
 
 
 CACHE_VERSION = 1

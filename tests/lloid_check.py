@@ -72,3 +72,20 @@ def check_peaks(pk, z_ref: np.ndarray, F: int, e_abs: float, threshold: float = 
         np.testing.assert_allclose(p.im, val.imag, rtol=0, atol=4 * e_abs + 1e-6)
         thr_ok = np.abs(pmax - threshold) > 2 * e_abs
         assert np.array_equal(p.above[thr_ok].astype(bool), (pmax >= threshold)[thr_ok])
+
+
+def _oracle_stride(args):
+    bank, x, F, k = args
+    from threadpoolctl import threadpool_limits
+    cfg = O.OracleConfig(F)
+    with threadpool_limits(1):
+        return np.stack([O.lloid_filter(x[d], bank, cfg, n_strides=1, first_stride=k)[0] for d in range(x.shape[0])])
+
+
+def oracle_series(banks, x: np.ndarray, F: int, k: int, workers: int = 16):
+    """Oracle complex SNR [n_det, M, F] of stride k for each bank, one bank
+    per worker process (one BLAS thread each)."""
+    import multiprocessing as mp
+    xs = np.ascontiguousarray(x[:, :(k + 1) * F])
+    with mp.get_context("spawn").Pool(min(workers, len(banks))) as pool:
+        return pool.map(_oracle_stride, [(b, xs, F, k) for b in banks], chunksize=1)
