@@ -327,6 +327,58 @@ def svd_measure(reps: int = 3, rows: int = 2048, n: int = 1024, rank: int = 40, 
                          "frac": flops / (ms / 1e3) / 1e12 / 78.6}}
 
 
+def grad_measure(reps: int = 3, refine_steps: int = 0):
+    """The gradient workload: the realistic bank (1024 templates, 5 rates)
+    at half its basis counts (L = 20/30/40/50/60), 64 s of strain at
+    4096 Hz, target = the FP32 output of the same bank at its full basis
+    counts.  Times lloid_grad (forward over the 64 strides with capture,
+    residual, transposed chain and the dW / dU contractions, synchronised)
+    as the mean of `reps` calls after one untimed, and optionally
+    `refine_steps` steps of refinement with FP64 re-orthonormalisation."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2511_04730_amd import LloidPlan
+    F, T = 4096, 64
+    full = synth.config2(duration_s=T).banks[0]
+    half = synth.truncate_bank(full, synth.C4_BASIS)
+    x = torch.from_numpy(synth.gaussian_strain(4, 1, T * F).astype(np.float32)).cuda()
+    tp = LloidPlan([full], F, 1, "fp32", normalize=False)
+    tg = torch.empty((T, tp.series_floats), dtype=torch.float32, device="cuda")
+    for k in range(T):
+        tp.push(x[:, k * F:(k + 1) * F].contiguous(), series=tg[k])
+    torch.cuda.synchronize()
+    tp.close()
+    plan = LloidPlan([half], F, 1, "fp32", normalize=False)
+    loss, _, _ = plan.grad(x, tg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.grad(x, tg)
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    # forward flops of the segment and the backward's three contractions
+    # (dW = 2 G Y^T and dY = 2 W^T G per slice at its rate, dU a correlation
+    # of dY with the slice's stream)
+    M = half.n_templates
+    fwd = bwd = 0.0
+    for s in half.slices:
+        fwd += T * (2.0 * s.n_basis * s.n_taps * s.rate + 2.0 * 2 * M * s.n_basis * s.rate)
+        bwd += T * (2 * 2.0 * 2 * M * s.n_basis * s.rate + 2.0 * s.n_basis * s.n_taps * s.rate)
+    out = {"ms": ms, "templates": M, "seconds": T, "basis": [s.n_basis for s in half.slices], "loss": loss,
+           "flops": fwd + bwd, "tflops": (fwd + bwd) / (ms / 1e3) / 1e12}
+    if refine_steps:
+        from paper_2511_04730_amd.refine import refine
+        smax2 = max(float(np.linalg.norm(s.mixing, 2)) ** 2 for s in half.slices)
+        t0 = time.perf_counter()
+        losses, _, _ = refine(plan, [half], x, tg, steps=refine_steps, eta=0.25, eta_u=0.1 / smax2)
+        torch.cuda.synchronize()
+        out["refine"] = {"steps": refine_steps, "seconds": time.perf_counter() - t0, "loss_first": losses[0],
+                         "loss_last": losses[-1],
+                         "monotone": all(b <= a * (1 + 1e-7) for a, b in zip(losses, losses[1:]))}
+    plan.close()
+    return out
+
+
 def gpu_stride_series(plan, strides, k: int):
     """The plan's series of stride k (fresh run of strides 0..k), per bank
     and detector 0, as complex128 host arrays."""
@@ -451,6 +503,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--xi2", type=int, default=-1,
                     help="also time xi^2, coincidence, whitening and SVD construction (-1: all but the largest workload)")
+    ap.add_argument("--grad-leg", type=int, default=0,
+                    help="also time the gradient on the realistic bank at half rank (64 s)")
+    ap.add_argument("--refine-steps", type=int, default=0, help="with --grad-leg: refinement steps to time")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     args = ap.parse_args()
@@ -578,6 +633,11 @@ def main() -> int:
         svd = svd_measure()
         log(f"svd bank construction: {svd['ms']:.2f} ms per slice")
 
+    grad = None
+    if args.grad_leg:
+        grad = grad_measure(refine_steps=args.refine_steps)
+        log(f"gradient: {grad['ms']:.1f} ms per call ({grad['tflops']:.2f} TFLOP/s)")
+
     base = err = zs = None
     if not args.no_cpu_baseline:
         base, err, zs = parity_and_baseline(plan, w, x, strides, k_par, args.cpu_seconds)
@@ -626,6 +686,7 @@ def main() -> int:
         "coincidence": coinc,
         "whitening": whiten,
         "svd_bank": svd,
+        "gradient": grad,
         "snr_err": err,
         "compare": compare,
         "baseline_loop": loop,

@@ -18,9 +18,14 @@ from .plan import LloidPlan, orthonormalize, quantize_fp8_rows
 
 
 def refine(plan: LloidPlan, banks: Sequence, strain, target, steps: int, eta: float, log=None,
-           quantize: Optional[str] = None):
+           quantize: Optional[str] = None, eta_u: Optional[float] = None):
     """Returns the loss before every step and after the last one, and the
     refined float64 (U, W) per slice (cuda tensors).
+
+    eta_u: step of the bases (default eta).  The curvature of the loss in U
+    scales with the squared singular values folded into W, in W with the
+    basis outputs' variance, so a bank with large singular values needs a
+    much smaller basis step (about eta / sigma_max^2) than mixing step.
 
     quantize="fp8": refinement for the FP8 form.  Every basis is held at
     its FP8 values (quantize_fp8_rows; the FP8 form converts them exactly)
@@ -31,6 +36,7 @@ def refine(plan: LloidPlan, banks: Sequence, strain, target, steps: int, eta: fl
     re-rounds every value.)"""
     import torch
     lr = eta / strain.shape[1]
+    lr_u = (eta if eta_u is None else eta_u) / strain.shape[1]
     U, W = bank_parameters(banks)
     if quantize is not None:
         assert quantize == "fp8"
@@ -47,7 +53,7 @@ def refine(plan: LloidPlan, banks: Sequence, strain, target, steps: int, eta: fl
                 W[i] -= lr * W[i].grad
                 W[i].grad = None
                 if quantize is None:
-                    U[i] -= lr * U[i].grad
+                    U[i] -= lr_u * U[i].grad
                     U[i].grad = None
                     orthonormalize(U[i].detach(), W[i].detach())
     with torch.no_grad():
