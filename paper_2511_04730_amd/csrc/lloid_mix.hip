@@ -198,7 +198,8 @@ struct Mix16 {
     static constexpr int RING_G = 8;       // ring outputs per 16-byte group
     struct ASrc {
         __amdgpu_buffer_rsrc_t wh, wl;
-        int va[kRB];
+        int va0;       // per lane: row block 0 of this wave, lane group's K offset
+        int mstride;   // bytes from one 16-row block to the next (wave-uniform)
     };
     struct FragA {
         T8 h[kRB], l[SPLIT_W ? kRB : 1];
@@ -210,14 +211,14 @@ struct Mix16 {
         const uint32_t wbytes = (uint32_t)ms.rows_pad * ms.Lpad * 2;
         s.wh = buffer_rsrc(ms.Whi, wbytes);
         if constexpr (SPLIT_W) s.wl = buffer_rsrc(ms.Wlo, wbytes);
-#pragma unroll
-        for (int m = 0; m < kRB; ++m) s.va[m] = (((r0 >> 4) + m) * (ms.Lpad / 8) + lg) * 256 + 16 * li;
+        s.mstride = (ms.Lpad / 8) * 256;
+        s.va0 = ((r0 >> 4) * (ms.Lpad / 8) + lg) * 256 + 16 * li;
     }
     static __device__ __forceinline__ void load_a(FragA &f, const ASrc &s, int l0) {
 #pragma unroll
         for (int m = 0; m < kRB; ++m) {
-            f.h[m] = buffer_load16<T8>(s.wh, s.va[m], l0 * 32);
-            if constexpr (SPLIT_W) f.l[m] = buffer_load16<T8>(s.wl, s.va[m], l0 * 32);
+            f.h[m] = buffer_load16<T8>(s.wh, s.va0, l0 * 32 + m * s.mstride);
+            if constexpr (SPLIT_W) f.l[m] = buffer_load16<T8>(s.wl, s.va0, l0 * 32 + m * s.mstride);
         }
     }
     // column block cb of an LDS stage [PLANES][4 groups][ncs][16 bytes]
@@ -300,6 +301,19 @@ struct Mix16 {
             acc[m] = mfma16(ah, k.h, acc[m]);
         }
     }
+};
+
+// Per slice of the staged (16-bit) contraction: the basis-output ring's
+// buffer resource and per-lane offsets of the y copies, and W~'s operand source.
+template <typename Op>
+struct StageSrc {
+    __amdgpu_buffer_rsrc_t ry;
+    int plane;   // bytes per ring plane
+    int cap16;   // bytes per K group of the ring
+    int vbase;   // per lane: first copy; copy cq < nq - 1 adds 1024 cq
+    int vlast;   // per lane: the last copy (clamped to the window)
+    int Lpad;
+    typename Op::ASrc as;
 };
 
 // ------------------------------------------------------------------ kernel
@@ -390,42 +404,70 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 const int ncopy = Op::PLANES * 4 * nq;
                 const int stage_bytes = ncopy * 1024;                // <= LVL_BYTES / 2
                 const uint32_t rate = (uint32_t)B.rate[j];
-                auto issue = [&](int sl, int l0, int so, typename Op::FragA &fa) {
+                // Per slice (set up once when the contraction reaches it): the
+                // ring's buffer resource and, per lane, the byte offset of each
+                // of its (up to four) 64-column copies.  Wave w copies K group
+                // w of every plane; the step over basis rows is the scalar
+                // offset alone.
+                using YCtx = StageSrc<Op>;
+                auto prepare = [&](int sl, YCtx &c) {
                     const MixSlice &ms = slices[sl];
                     const uint32_t cap2 = 2u * (uint32_t)ms.capY;
                     const uint32_t pos0 = (kstr * rate + (uint32_t)lo) & (uint32_t)(ms.capY - 1);
                     const char *ring = static_cast<const char *>(ms.Y) + (int64_t)it.det * ms.ydet * 4;
-                    const uint32_t plane = cap2 * (uint32_t)ms.Lpad * (16 / Op::RING_G);   // bytes per plane
-                    const __amdgpu_buffer_rsrc_t ry = buffer_rsrc(ring, plane * Op::PLANES);
-                    const int soff = (l0 / Op::RING_G) * (int)cap2 * 16;
+                    const uint32_t plane = cap2 * (uint32_t)ms.Lpad * (16 / Op::RING_G);
+                    c.plane = (int)plane;
+                    c.ry = buffer_rsrc(ring, plane * Op::PLANES);
+                    c.cap16 = (int)cap2 * 16;
                     // columns past the window re-read its last sample (finite,
                     // never stored): every copy stays inside the window, which is
-                    // contiguous in the mirror ring (n <= capY, checked at plan time)
-                    for (int q = wave; q < ncopy; q += 4) {
-                        const int pl = q / (4 * nq), kg = (q / nq) & 3, cq = q - (q / nq) * nq;
-                        const uint32_t c = (uint32_t)min(cq * 64 + lane, n - 1);
-                        const int voff = (int)(((uint32_t)kg * cap2 + pos0 + c) * 16u + pl * plane);
-                        __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                            ry, (__attribute__((address_space(3))) void *)(lds + so + ((pl * 4 + kg) * ncs + cq * 64) * 16),
-                            16, voff, soff, 0, 0);
+                    // contiguous in the mirror ring (n <= capY, checked at plan time).
+                    // Only the last copy can reach past it (n > ncs - 64).
+                    const uint32_t g0 = (uint32_t)wave * cap2 + pos0;
+                    c.vbase = (int)((g0 + (uint32_t)lane) * 16u);
+                    c.vlast = (int)((g0 + (uint32_t)min((nq - 1) * 64 + lane, n - 1)) * 16u);
+                    c.Lpad = ms.Lpad;
+                    Op::init_a(c.as, ms, it.r0 + rw, li, lg);
+                };
+                auto issue = [&](const YCtx &c, int l0, int so, typename Op::FragA &fa) {
+                    // the builtin's operands are plain locals: taken straight from
+                    // the struct, the host pass drops the kernel's instantiation
+                    const int soff = (l0 / Op::RING_G) * c.cap16;
+                    __amdgpu_buffer_rsrc_t ry = c.ry;
+                    const int vb = c.vbase, vl = c.vlast, pln = c.plane;
+#pragma unroll
+                    for (int pl = 0; pl < Op::PLANES; ++pl) {
+                        typedef __attribute__((address_space(3))) void *lds_ptr;
+                        char *dst = lds + so + (pl * 4 + wave) * ncs * 16;
+                        const int sp = soff + pl * pln;
+                        // copies 0 .. nq - 2 (wave-uniform count), then the last.  The
+                        // immediate offset moves both the global and the LDS address.
+                        if (nq > 1) __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, (lds_ptr)dst, 16, vb, sp, 0, 0);
+                        if (nq > 2) __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, (lds_ptr)dst, 16, vb, sp, 1024, 0);
+                        if (nq > 3) __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, (lds_ptr)dst, 16, vb, sp, 2048, 0);
+                        __builtin_amdgcn_raw_ptr_buffer_load_lds(ry, (lds_ptr)(dst + (nq - 1) * 1024), 16, vl, sp, 0, 0);
                     }
-                    typename Op::ASrc as;
-                    Op::init_a(as, ms, it.r0 + rw, li, lg);
-                    Op::load_a(fa, as, l0);
+                    Op::load_a(fa, c.as, l0);
                 };
                 int cs = sb, cl = 0, so = 0;
+                YCtx yc;   // the slice of the last chunk issued
                 typename Op::FragA fa0, fa1;
-                if (sb < se) issue(cs, cl, so, fa0);
+                if (sb < se) {
+                    prepare(sb, yc);
+                    issue(yc, 0, 0, fa0);
+                }
                 auto step = [&](const typename Op::FragA &fcur, typename Op::FragA &fnext) -> bool {
                     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this chunk's copies and W~ have landed
                     __syncthreads();                      // ... for every wave; the other stage is free
                     int ns = cs, nl = cl + Op::K;
-                    if (nl >= slices[ns].Lpad) {
+                    bool more = true;
+                    if (nl >= yc.Lpad) {
                         ++ns;
                         nl = 0;
+                        more = ns < se;
+                        if (more) prepare(ns, yc);
                     }
-                    const bool more = ns < se;
-                    if (more) issue(ns, nl, so ^ stage_bytes, fnext);
+                    if (more) issue(yc, nl, so ^ stage_bytes, fnext);
                     const char *st = lds + so;
 #pragma unroll
                     for (int i = 0; i < kCB; ++i) {
