@@ -23,7 +23,8 @@
 //         on the fly, d = d_hi + d_lo;
 //           SPLIT_U (bf16x3): U_hi d_lo + U_lo d_hi + U_hi d_hi
 //           otherwise (fp16): U d_lo + U d_hi
-//   FP8   v_mfma_f32_16x16x32_fp8_fp8 (OCP e4m3 on gfx950): the basis rows
+//   FP8   v_mfma_f32_16x16x128_f8f6f4 on e4m3 operands (OCP e4m3 on gfx950,
+//         128 taps per instruction): the basis rows
 //         hold e4m3(u_l 2^e_l) with one power-of-two scale per basis vector
 //         (largest |u| near the e4m3 maximum 448), the strain is scaled by
 //         kFp8StrainScale and split into two e4m3 parts; outputs are
@@ -43,11 +44,12 @@
 
 namespace lloid {
 
-constexpr int kCB = kCorrTQ / 64;   // column blocks per wave (four waves)
+constexpr int kCB = kCorrTQ / 64;   // column blocks per wave (four waves); the FP8 form: kCorrTQ8 / 64
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 constexpr float kFp8StrainScale = 8.0f;
 
@@ -56,15 +58,16 @@ __device__ __forceinline__ uint32_t fp8_byte(float v) {
 }
 __device__ __forceinline__ float fp8_value(uint32_t b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
 
-// strain samples of a stage: kCorrTQ + TK (+ 8 for the shifted copies)
-template <int TK>
+// strain samples of a stage: TQ + TK (+ 8 for the shifted copies)
+template <int TK, int TQ = kCorrTQ>
 struct StrainRegs {
-    static constexpr int N = kCorrTQ + TK;
+    static constexpr int N = TQ + TK;
     static constexpr int PER = (N + 255) / 256;
     float v[PER];
-    // samples past the item's columns + TK are never used: zeros, unread
-    __device__ __forceinline__ void load(const CorrItem &it, int64_t p0, int tid) {
-        const int lim = min(N, it.ncols + TK);
+    // samples past the item's columns + the stage's taps are never used:
+    // zeros, unread (taps < TK when a stage reaches past the item's end)
+    __device__ __forceinline__ void load(const CorrItem &it, int64_t p0, int tid, int taps = TK) {
+        const int lim = min(N, it.ncols + taps);
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = tid + 256 * i;
@@ -75,6 +78,7 @@ struct StrainRegs {
 
 // ------------------------------------------------------------------ FP32
 struct CorrF32 {
+    static constexpr int CB = kCB;
     static constexpr int TK = 32;
     static constexpr int US = TK + 2;   // 16 rows x 2 taps of a half-wave in distinct banks
     struct Smem {
@@ -115,7 +119,7 @@ struct CorrF32 {
             if (e < StrainRegs<TK>::N) s.d[e] = g.d.v[i];
         }
     }
-    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][kCB], int mb, int ncb,
+    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][CB], int mb, int ncb,
                                                    int wave, int li, int lg) {
 #pragma unroll
         for (int ks = 0; ks < TK; ks += 4) {
@@ -139,6 +143,7 @@ struct CorrF32 {
 // ---------------------------------------------------------------- 16-bit
 template <typename T, typename T8, bool SPLIT_U>
 struct Corr16 {
+    static constexpr int CB = kCB;
     static constexpr int TK = 64;
     static constexpr int US = TK + 8;   // 144 B rows: 16-B fragment reads of a half-wave in distinct banks
     static constexpr int DL = kCorrTQ + TK + 8;
@@ -196,7 +201,7 @@ struct Corr16 {
             }
         }
     }
-    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][kCB], int mb, int ncb,
+    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][CB], int mb, int ncb,
                                                    int wave, int li, int lg) {
 #pragma unroll
         for (int ks = 0; ks < TK; ks += 32) {
@@ -230,10 +235,15 @@ struct Corr16 {
 };
 
 // ------------------------------------------------------------------ FP8
+// v_mfma_f32_16x16x128_f8f6f4 with both operands e4m3 (no block scales):
+// 128 taps per MFMA, lane group g supplying taps 32 g .. 32 g + 31 of its row
+// (A) or column (B) as 32 bytes.  A stage is 128 taps; its tap range past
+// the item's end (a split of 64 x odd taps) reads as zero on both sides.
 struct Corr8 {
-    static constexpr int TK = 64;
-    static constexpr int US = TK + 16;   // bytes per basis row
-    static constexpr int DL = kCorrTQ + TK + 8;
+    static constexpr int CB = kCorrTQ8 / 64;   // 256 columns per item: the accumulators of 128-tap fragments fit
+    static constexpr int TK = 128;
+    static constexpr int US = TK + 16;   // bytes per basis row (16-byte aligned rows)
+    static constexpr int DL = kCorrTQ8 + TK + 8;
     struct Smem {
         uint8_t U[kCorrMB * 16 * US];
         uint8_t Dh[8 * DL];
@@ -242,18 +252,20 @@ struct Corr8 {
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
     struct Regs {
         u32x2 u[PER];
-        StrainRegs<TK> d;
+        StrainRegs<TK, kCorrTQ8> d;
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
         const uint8_t *gu = static_cast<const uint8_t *>(it.Uhi);
+        const int kmax = it.klen - kk;   // taps of this stage inside the item
 #pragma unroll
         for (int i = 0; i < PER; ++i) {
             const int e = tid + 256 * i;
             const int r = e / (TK / 8), c8 = e % (TK / 8);
-            if (r < it.mb * 16)
+            g.u[i] = u32x2{0u, 0u};
+            if (r < it.mb * 16 && 8 * c8 < kmax)
                 g.u[i] = ld_global<u32x2>(gu + (int64_t)(it.r0 + r) * it.Npad + it.k0 + kk + 8 * c8);
         }
-        g.d.load(it, p0, tid);
+        g.d.load(it, p0, tid, min(TK, kmax));
     }
     static __device__ __forceinline__ void lstore(const Regs &g, Smem &s, const CorrItem &it, int tid) {
 #pragma unroll
@@ -264,9 +276,9 @@ struct Corr8 {
         }
         // one byte per sample and copy
 #pragma unroll
-        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
+        for (int k = 0; k < StrainRegs<TK, kCorrTQ8>::PER; ++k) {
             const int e = tid + 256 * k;
-            if (e >= StrainRegs<TK>::N) continue;
+            if (e >= StrainRegs<TK, kCorrTQ8>::N) continue;
             // saturate at the e4m3 maximum (whitened samples beyond 56 sigma)
             const float v = fminf(fmaxf(g.d.v[k] * kFp8StrainScale, -448.0f), 448.0f);
             const uint32_t h = fp8_byte(v);
@@ -281,28 +293,32 @@ struct Corr8 {
             }
         }
     }
-    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][kCB], int mb, int ncb,
+    // 32 bytes of a shifted strain copy starting at element idx (8-byte aligned reads)
+    static __device__ __forceinline__ i32x8 hankel32(const uint8_t *D, int idx) {
+        const int sft = idx & 7;
+        typedef int i32x2 __attribute__((ext_vector_type(2)));
+        const i32x2 *p = reinterpret_cast<const i32x2 *>(&D[sft * DL + idx - sft]);
+        const i32x2 a = p[0], b = p[1], c = p[2], d = p[3];
+        return i32x8{a[0], a[1], b[0], b[1], c[0], c[1], d[0], d[1]};
+    }
+    static __device__ __forceinline__ void compute(const Smem &s, floatx4 (&acc)[kCorrMB][CB], int mb, int ncb,
                                                    int wave, int li, int lg) {
+        i32x8 a[kCorrMB];
 #pragma unroll
-        for (int ks = 0; ks < TK; ks += 32) {
-            long bh[kCB], bl[kCB];
+        for (int m = 0; m < kCorrMB; ++m) {
+            if (m >= mb) continue;
+            a[m] = *reinterpret_cast<const i32x8 *>(&s.U[(m * 16 + li) * US + 32 * lg]);   // 16-byte aligned
+        }
 #pragma unroll
-            for (int i = 0; i < kCB; ++i) {
-                const int idx = (wave + 4 * i) * 16 + li + ks + 8 * lg;
-                const int sft = idx & 7;
-                bh[i] = *reinterpret_cast<const long *>(&s.Dh[sft * DL + idx - sft]);
-                bl[i] = *reinterpret_cast<const long *>(&s.Dl[sft * DL + idx - sft]);
-            }
+        for (int i = 0; i < CB; ++i) {
+            if (i >= ncb) continue;
+            const int idx = (wave + 4 * i) * 16 + li + 32 * lg;
+            const i32x8 bh = hankel32(s.Dh, idx), bl = hankel32(s.Dl, idx);
 #pragma unroll
             for (int m = 0; m < kCorrMB; ++m) {
                 if (m >= mb) continue;
-                const long a = *reinterpret_cast<const long *>(&s.U[(m * 16 + li) * US + ks + 8 * lg]);
-#pragma unroll
-                for (int i = 0; i < kCB; ++i) {
-                    if (i >= ncb) continue;
-                    acc[m][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bl[i], acc[m][i], 0, 0, 0);
-                    acc[m][i] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, bh[i], acc[m][i], 0, 0, 0);
-                }
+                acc[m][i] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[m], bl, acc[m][i], 0, 0, 0, 0, 0, 0);
+                acc[m][i] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a[m], bh, acc[m][i], 0, 0, 0, 0, 0, 0);
             }
         }
     }
@@ -351,13 +367,14 @@ __global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lg = lane >> 4;
     // this wave's column blocks cb = wave + 4 i, i < ncb
-    const int ncb = min(kCB, max(0, (((it.ncols + 15) >> 4) - wave + 3) >> 2));
+    constexpr int CB = Op::CB;
+    const int ncb = min(CB, max(0, (((it.ncols + 15) >> 4) - wave + 3) >> 2));
 
-    floatx4 acc[kCorrMB][kCB];
+    floatx4 acc[kCorrMB][CB];
 #pragma unroll
     for (int m = 0; m < kCorrMB; ++m)
 #pragma unroll
-        for (int i = 0; i < kCB; ++i) acc[m][i] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int i = 0; i < CB; ++i) acc[m][i] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
     typename Op::Regs g;
@@ -371,7 +388,7 @@ __global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict
     }
     const int64_t q0 = kstr * it.f + it.la + it.col0;
 #pragma unroll
-    for (int i = 0; i < kCB; ++i) {
+    for (int i = 0; i < CB; ++i) {
         if (i >= ncb) continue;
         const int c = (wave + 4 * i) * 16 + li;
         if (c >= it.ncols) continue;

@@ -13,6 +13,7 @@ namespace lloid {
 constexpr int kMaxLevels = 12;        // distinct rates per bank (top included)
 constexpr int kMaxBasis = 160;        // L^s limit, and per bank and rate (ABI)
 constexpr int kCorrTQ = 512;          // correlation item: output columns (128 per wave)
+constexpr int kCorrTQ8 = 256;         // ... in the FP8 form (64 per wave)
 constexpr int kCorrMB = 4;            // correlation item: 16-row blocks of basis vectors
 constexpr int kCorrTK = 64;           // tap padding of the basis rows
 constexpr int kCorrSplitK = 512;      // taps per correlation work item

@@ -233,7 +233,8 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
             for (int sp = 0; sp < s.nsplit; ++sp) {
                 const int k0 = sp * P->ksplit;
                 const int klen = std::min(P->ksplit, s.Npad - k0);
-                for (int c0 = 0; c0 < f; c0 += P->corr_cols)
+                const int cols = P->precision == LLOID_FP8_BF16 ? std::min(P->corr_cols, kCorrTQ8) : P->corr_cols;
+                for (int c0 = 0; c0 < f; c0 += cols)
                 for (int r0 = 0; r0 < s.Lpad; r0 += kCorrMB * 16) {
                     CorrItem it{};
                     it.U = s.U32;
@@ -248,7 +249,7 @@ lloid_status build_corr_tables(lloid_plan *P, hipStream_t st) {
                     it.cap = r.cap;
                     it.f = f;
                     it.col0 = c0;
-                    it.ncols = std::min(P->corr_cols, f - c0);
+                    it.ncols = std::min(cols, f - c0);
                     it.k0 = k0;
                     it.klen = klen;
                     it.mb = std::min(kCorrMB, (s.Lpad - r0) / 16);

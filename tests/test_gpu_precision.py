@@ -108,3 +108,40 @@ def test_set_slice_matches_plan_creation(plan_cls, precision):
         assert np.array_equal(z[b], z_ref[b]), f"bank {b}"
         for pa, pb in zip(p[b], p_ref[b]):
             assert np.array_equal(pa.index, pb.index) and np.array_equal(pa.snr, pb.snr)
+
+
+@pytest.mark.parametrize("split", [0, 576])
+def test_fp8_basis_outputs_at_fp8_values(plan_cls, split):
+    """The FP8 correlation computes exactly the correlation of the FP8 values:
+    the basis rows at their e4m3 values with the per-vector scale
+    (oracle quantize_fp8_rows) and the decimated stream at its two-part e4m3
+    value (hi = e4m3(8 d), lo = e4m3(8 d - hi), saturated at 448), summed
+    in FP32 and kept as BF16 hi + lo in the ring: within 2e-4 of the
+    oracle's correlate step on those values (the GPU decimates in FP32, which
+    can move a sample across an e4m3 rounding boundary).  Slices of 1088 and
+    1984 taps (odd multiples of 64: the last 128-tap stage of an item reaches
+    past its end) and a 576-tap split (nine 64-tap blocks per item)."""
+    from oracle import lloid as O
+    F = 2048
+    bank = synth.chirp_bank(F, 8, 30.0, (2.0, 4.0), [(2048, 0.0, 1088, 16), (512, 0.5, 1984, 16)],
+                            seed=[31, 1, 0])
+    x = synth.gaussian_strain(31, 1, 8 * F)
+    plan = plan_cls([bank], F, 1, "fp8_bf16", normalize=False)
+    if split:
+        plan.set_option("corr_split", split)
+    run_gpu(plan, x, 7, 1)
+    k = 8
+    for si, s in enumerate(bank.slices):
+        D, f = F // s.rate, s.rate
+        la = plan.query(9, si)
+        q_lo, q_hi = k * f + la - min(400, f), k * f + la
+        y_gpu = plan.basis_out(si, s.n_basis, 0, q_lo, q_hi)
+        d_lo = q_lo - s.delay - s.n_taps + 1
+        d = O.downsample(x[0], D, d_lo, q_hi - s.delay)
+        v = np.clip(d * 8.0, -448.0, 448.0)
+        hi = O.e4m3_round(v)
+        dq = (hi + O.e4m3_round(v - hi)) / 8.0
+        y_ref = O.correlate(O.quantize_fp8_rows(s.basis), dq, d_lo, s.delay, q_lo, q_hi)
+        err = np.abs(y_gpu - y_ref).max() / np.abs(y_ref).max()
+        print(f"split {split} slice {si} ({s.rate} Hz, {s.n_taps} taps): rel err {err:.3e}", flush=True)
+        assert err < 2e-4
