@@ -69,7 +69,9 @@ KERNEL_SOURCES = {"mix": ["lloid_mix.hip", "lloid_internal.h", "lloid_device.h",
                   "corr": ["lloid_corr.hip", "lloid_internal.h", "lloid_device.h", "lloid_mfma.h"],
                   "xi2": ["lloid_xi2.hip", "lloid_xi2.h", "lloid_internal.h", "lloid_device.h"],
                   "window_trigger": ["lloid_coinc.hip", "lloid_coinc.h", "lloid_internal.h", "lloid_device.h"],
-                  "whitening": ["lloid_whiten.hip", "lloid_whiten.h"]}
+                  "whitening": ["lloid_whiten.hip", "lloid_whiten.h"],
+                  "down": ["lloid_kernels.hip", "lloid_internal.h", "lloid_device.h"],
+                  "peaks": ["lloid_kernels.hip", "lloid_internal.h", "lloid_device.h"]}
 
 
 def source_digest(kernel: str) -> str:
@@ -578,6 +580,7 @@ def main() -> int:
     for k in ("down", "corr", "mix", "peaks"):
         if k in kernel_ms:
             roofs[k] = roof(kf.get(k, 0.0), kb[k], kernel_ms[k], kernel_peak(args.precision, k))
+            roofs[k]["traffic"] = measured_traffic(k, args.workload, args.precision)
     dom = max(("corr", "mix"), key=lambda k: kernel_ms.get(k, 0.0))
     d = roofs[dom]
     if d["bound"] == "hbm":
