@@ -305,10 +305,11 @@ def whiten_measure(w, reps: int):
 def svd_measure(reps: int = 3, rows: int = 2048, n: int = 1024, rank: int = 40, iters: int = 30):
     """SVD bank construction (Sec. II.C.1) for one slice of the realistic
     bank's shape (2M = 2048 real templates, N = 1024 taps, L = 40): a seeded
-    matrix with a geometrically decaying spectrum, `iters` subspace
-    iterations, mean wall time over `reps` calls (each synchronises).
-    Algorithmic flops per call: iters x (2 products of 2 rows N L + two
-    CholeskyQR passes of 2 L^2 N + L^3 / 3) + the final product."""
+    matrix with the spectrum 0.8^k, `iters` subspace iterations, mean wall
+    time over `reps` calls (each synchronises), and the residual
+    ||H - W U||_F over the optimum.  Algorithmic flops per call: iters x (2
+    products of 2 rows N L + one CholeskyQR pass on each half step, 2 L^2
+    rows and 2 L^2 N, + 2 L^3 / 3) + the final product."""
     import numpy as np
     import torch
     from paper_2511_04730_amd.plan import svd_basis
@@ -317,14 +318,19 @@ def svd_measure(reps: int = 3, rows: int = 2048, n: int = 1024, rank: int = 40, 
     B = np.linalg.qr(g.standard_normal((n, rank * 2)))[0]
     H = torch.from_numpy((A * 0.8 ** np.arange(rank * 2)) @ B.T).cuda()
     start = torch.from_numpy(g.standard_normal((rank, n))).cuda()
-    svd_basis(H, rank, start, iters=iters)
+    U, W = svd_basis(H, rank, start, iters=iters)
     torch.cuda.synchronize()
+    # residual against the optimum: the spectrum is 0.8^k by construction,
+    # so the best rank-L residual is sqrt(sum_{k >= L} 0.8^(2k))
+    resid = float(torch.linalg.norm(H - W @ U))
+    opt = float(np.sqrt(np.sum(0.8 ** (2 * np.arange(rank, 2 * rank)))))
     t0 = time.perf_counter()
     for _ in range(reps):
         svd_basis(H, rank, start, iters=iters)
     ms = (time.perf_counter() - t0) / reps * 1e3
-    flops = iters * (4 * rows * n * rank + 2 * (2 * rank * rank * n + rank ** 3 / 3)) + 2 * rows * n * rank
+    flops = iters * (4 * rows * n * rank + 2 * rank * rank * (rows + n) + 2 * rank ** 3 / 3) + 2 * rows * n * rank
     return {"ms": ms, "rows": rows, "taps": n, "rank": rank, "iterations": iters,
+            "residual_over_optimum": resid / opt,
             "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
                          "frac": flops / (ms / 1e3) / 1e12 / 78.6}}
 

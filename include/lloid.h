@@ -235,9 +235,9 @@ lloid_status lloid_orthonormalize(double *U_dev, int32_t L, int32_t N, double *W
 /* The same re-orthonormalisation for callers that cannot allocate device
  * memory (code under HIP graph capture, tight refinement loops, harnesses
  * that forbid hipMalloc): no hipMalloc, hipFree or allocating library call,
- * and no synchronisation; it only enqueues on `stream`.  Its Gram matrix
- * and Cholesky factor live in a static device array of the library
- * (205 056 bytes per GPU, held until the process ends), which every call on
+ * and no synchronisation; it only enqueues on `stream`.  Its Gram matrix,
+ * Cholesky factor and its inverse live in a static device array of the library
+ * (409 856 bytes per GPU, held until the process ends), which every call on
  * that GPU shares: calls that overlap on one GPU race and must be ordered
  * by the caller (one stream, or events).  Results are those of
  * lloid_orthonormalize (same kernels).

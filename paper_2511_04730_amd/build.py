@@ -13,6 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "liblloid.so")
 SOURCES = ["lloid_plan.hip", "lloid_kernels.hip", "lloid_corr.hip", "lloid_mix.hip", "lloid_grad.hip",
+           "lloid_linalg.hip",
            "lloid_xi2.hip", "lloid_coinc.hip",
            "lloid_whiten.hip"]
 

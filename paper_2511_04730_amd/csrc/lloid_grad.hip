@@ -200,141 +200,6 @@ hipError_t launch_sum_parts(hipStream_t st, const float *part, int32_t nsplit, i
     return hipGetLastError();
 }
 
-// -------------------------------------------- FP64 CholeskyQR2 pieces
-// G[a][b] = sum_n U[a][n] U[b][n], U [L][N] row-major (ld = N)
-__global__ __launch_bounds__(256) void gram_f64_kernel(const double *__restrict__ U, int32_t L, int32_t N,
-                                                       double *__restrict__ G) {
-    __shared__ double red[256];
-    const int a = blockIdx.x, b = blockIdx.y;
-    if (b < a) return;
-    double acc = 0.0;
-    for (int n = threadIdx.x; n < N; n += 256) acc = fma(U[(int64_t)a * N + n], U[(int64_t)b * N + n], acc);
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        G[a * L + b] = red[0];
-        G[b * L + a] = red[0];
-    }
-}
-
-// In-place lower Cholesky factor C (G = C C^T) of an L x L SPD matrix, one
-// work group, column by column.  A pivot that is not positive is replaced
-// by 1 (so the passes run on) and, if info[0] is still 0, recorded there as
-// its column + 1; info is never reset here, so a breakdown stays reported
-// until the caller clears it (launch_clear_info).
-// The same factorisation with G held in LDS, for L <= kCholLds (the column
-// updates then read LDS instead of global memory).
-constexpr int kCholLds = 88;   // 88^2 doubles = 61952 bytes of static LDS
-__global__ __launch_bounds__(256) void cholesky_lds_f64_kernel(double *__restrict__ G, int32_t L, int32_t *info) {
-    __shared__ double sG[kCholLds * kCholLds];
-    __shared__ double piv;
-    for (int e = threadIdx.x; e < L * L; e += 256) sG[e] = G[e];
-    for (int j = 0; j < L; ++j) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double d = sG[j * L + j];
-            for (int k = 0; k < j; ++k) d -= sG[j * L + k] * sG[j * L + k];
-            if (!(d > 0.0)) {
-                if (info[0] == 0) info[0] = j + 1;
-                d = 1.0;
-            }
-            piv = sqrt(d);
-            sG[j * L + j] = piv;
-        }
-        __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < L; i += 256) {
-            double v = sG[i * L + j];
-            for (int k = 0; k < j; ++k) v -= sG[i * L + k] * sG[j * L + k];
-            sG[i * L + j] = v / piv;
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < L * L; e += 256) G[e] = (e % L > e / L) ? 0.0 : sG[e];   // lower triangle
-}
-
-__global__ __launch_bounds__(256) void cholesky_f64_kernel(double *__restrict__ G, int32_t L, int32_t *info) {
-    __shared__ double piv;
-    for (int j = 0; j < L; ++j) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double d = G[j * L + j];
-            for (int k = 0; k < j; ++k) d -= G[j * L + k] * G[j * L + k];
-            if (!(d > 0.0)) {
-                if (info[0] == 0) info[0] = j + 1;
-                d = 1.0;
-            }
-            piv = sqrt(d);
-            G[j * L + j] = piv;
-        }
-        __syncthreads();
-        for (int i = j + 1 + threadIdx.x; i < L; i += 256) {
-            double s = G[i * L + j];
-            for (int k = 0; k < j; ++k) s -= G[i * L + k] * G[j * L + k];
-            G[i * L + j] = s / piv;
-        }
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < L * L; e += 256)
-        if (e % L > e / L) G[e] = 0.0;   // clear the upper triangle
-}
-
-// U <- C^-1 U (forward substitution per column n)
-__global__ void trsm_lower_f64_kernel(const double *__restrict__ C, int32_t L, double *__restrict__ U, int32_t N) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= N) return;
-    for (int i = 0; i < L; ++i) {
-        double s = U[(int64_t)i * N + n];
-        for (int k = 0; k < i; ++k) s -= C[i * L + k] * U[(int64_t)k * N + n];
-        U[(int64_t)i * N + n] = s / C[i * L + i];
-    }
-}
-
-// W <- W C, W [rows][L]
-__global__ void right_mul_f64_kernel(double *__restrict__ W, int32_t rows, int32_t L, const double *__restrict__ C) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
-    double tmp[kMaxBasis];
-    for (int l = 0; l < L; ++l) tmp[l] = W[(int64_t)r * L + l];
-    for (int l = 0; l < L; ++l) {
-        double s = 0.0;
-        for (int k = l; k < L; ++k) s = fma(tmp[k], C[k * L + l], s);
-        W[(int64_t)r * L + l] = s;
-    }
-}
-
-__global__ void clear_info_kernel(int32_t *info, int32_t n) {
-    if ((int)threadIdx.x < n) info[threadIdx.x] = 0;
-}
-
-// A kernel rather than a memset, so that the clear can sit in a captured graph.
-hipError_t launch_clear_info(hipStream_t st, int32_t *info, int32_t n) {
-    hipLaunchKernelGGL(clear_info_kernel, dim3(1), dim3(64), 0, st, info, n);
-    return hipGetLastError();
-}
-
-// Two CholeskyQR passes; info[pass] receives the first failing column + 1
-// of that pass's factorisation if it is still 0 (cleared by the caller).
-hipError_t launch_cholesky_qr2(hipStream_t st, double *U, int32_t L, int32_t N, double *W, int32_t rows,
-                               double *G, int32_t *info) {
-    for (int pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(gram_f64_kernel, dim3(L, L), dim3(256), 0, st, U, L, N, G);
-        if (L <= kCholLds)
-            hipLaunchKernelGGL(cholesky_lds_f64_kernel, dim3(1), dim3(256), 0, st, G, L, info + pass);
-        else
-            hipLaunchKernelGGL(cholesky_f64_kernel, dim3(1), dim3(256), 0, st, G, L, info + pass);
-        hipLaunchKernelGGL(trsm_lower_f64_kernel, dim3((N + 255) / 256), dim3(256), 0, st, G, L, U, N);
-        if (rows > 0)   // rows == 0: orthonormalise U alone
-            hipLaunchKernelGGL(right_mul_f64_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, W, rows, L, G);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
-}
-
 }  // namespace lloid
 
 // ------------------------------------------- FP8 basis values (refinement)
@@ -374,102 +239,4 @@ extern "C" lloid_status lloid_quantize_fp8_rows(const double *U, int32_t rows, i
     hipLaunchKernelGGL(quantize_fp8_rows_kernel, dim3(rows), dim3(256), 0, static_cast<hipStream_t>(stream), U, cols,
                        Uq);
     return hipGetLastError() == hipSuccess ? LLOID_OK : LLOID_E_HIP;
-}
-
-// ------------------------------------------------ SVD bank construction
-// The rank-L truncation of a slice's template matrix H (rows x N, float64)
-// by subspace iteration: V <- orth((H^T H) V) with CholeskyQR2 after every
-// product; V's rows converge to an orthonormal basis of the top-L right
-// singular subspace (error ratio (sigma_{L+1} / sigma_L)^2 per iteration),
-// and W = H V^T, so that W V = H P_L, the best rank-L approximation.
-namespace {
-
-// T[r][l] = sum_n H[r][n] V[l][n]: one block per (r, l)
-__global__ __launch_bounds__(256) void h_vt_kernel(const double *__restrict__ H, const double *__restrict__ V,
-                                                   int32_t N, int32_t L, double *__restrict__ T) {
-    __shared__ double red[256];
-    const int r = blockIdx.x, l = blockIdx.y;
-    double s = 0.0;
-    for (int n = threadIdx.x; n < N; n += 256) s += H[(int64_t)r * N + n] * V[(int64_t)l * N + n];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) T[(int64_t)r * L + l] = red[0];
-}
-
-// part[p][l][n] = sum over rows r of split p of T[r][l] H[r][n]: one thread
-// per (l, n, p), so that the product fills the chip for few basis rows
-constexpr int kSvdSplit = 16;
-__global__ __launch_bounds__(256) void ht_t_kernel(const double *__restrict__ H, const double *__restrict__ T,
-                                                   int32_t rows, int32_t N, int32_t L, double *__restrict__ part) {
-    const int n = blockIdx.x * 256 + threadIdx.x, l = blockIdx.y, p = blockIdx.z;
-    if (n >= N) return;
-    const int r0 = (int)((int64_t)rows * p / kSvdSplit), r1 = (int)((int64_t)rows * (p + 1) / kSvdSplit);
-    double s = 0.0;
-    for (int r = r0; r < r1; ++r) s += T[(int64_t)r * L + l] * H[(int64_t)r * N + n];
-    part[((int64_t)p * L + l) * N + n] = s;
-}
-
-// V[l][n] = sum_p part[p][l][n] in a fixed order
-__global__ __launch_bounds__(256) void sum_splits_kernel(const double *__restrict__ part, int64_t plane,
-                                                         double *__restrict__ V) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= plane) return;
-    double s = 0.0;
-    for (int p = 0; p < kSvdSplit; ++p) s += part[p * plane + i];
-    V[i] = s;
-}
-
-}  // namespace
-
-extern "C" lloid_status lloid_svd_basis(const double *H, int32_t rows, int32_t N, int32_t L, int32_t iters, double *U,
-                                        double *W, void *stream) {
-    if (!H || !U || !W || rows < 1 || N < 1 || L < 1 || L > lloid::kMaxBasis || L > rows || L > N || iters < 1)
-        return LLOID_E_ARG;
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    double *T = nullptr, *G = nullptr, *part = nullptr;
-    int32_t *info = nullptr;
-    const int64_t plane = (int64_t)L * N;
-    if (hipMalloc(&T, sizeof(double) * rows * L) != hipSuccess) return LLOID_E_NOMEM;
-    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess || hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess ||
-        hipMalloc(&part, sizeof(double) * kSvdSplit * plane) != hipSuccess) {
-        (void)hipFree(T);
-        (void)hipFree(G);
-        (void)hipFree(info);
-        return LLOID_E_NOMEM;
-    }
-    int32_t h[2] = {0, 0}, bad = 0;
-    // cleared once: a breakdown in any pass since the start stays latched until the next check
-    hipError_t e = lloid::launch_clear_info(st, info, 2);
-    if (e == hipSuccess) e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);   // orthonormal start
-    for (int it = 0; it < iters && e == hipSuccess; ++it) {
-        hipLaunchKernelGGL(h_vt_kernel, dim3(rows, L), dim3(256), 0, st, H, U, N, L, T);
-        hipLaunchKernelGGL(ht_t_kernel, dim3((N + 255) / 256, L, kSvdSplit), dim3(256), 0, st, H, T, rows, N, L,
-                           part);
-        hipLaunchKernelGGL(sum_splits_kernel, dim3((unsigned)((plane + 255) / 256)), dim3(256), 0, st, part, plane, U);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = lloid::launch_cholesky_qr2(st, U, L, N, nullptr, 0, G, info);
-        if (e == hipSuccess && (it % 16 == 15 || it == iters - 1)) {   // a singular block stops the iteration
-            e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-            if (h[0] || h[1]) {
-                bad = 1;
-                break;
-            }
-        }
-    }
-    if (e == hipSuccess && !bad) {
-        hipLaunchKernelGGL(h_vt_kernel, dim3(rows, L), dim3(256), 0, st, H, U, N, L, W);
-        e = hipGetLastError();
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
-    }
-    (void)hipFree(T);
-    (void)hipFree(G);
-    (void)hipFree(info);
-    (void)hipFree(part);
-    if (e != hipSuccess) return LLOID_E_HIP;
-    return bad ? LLOID_E_STATE : LLOID_OK;
 }

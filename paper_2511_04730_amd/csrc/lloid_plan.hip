@@ -309,8 +309,8 @@ lloid_status validate(const lloid_config *c, const lloid_bank *banks, int32_t n_
 
 // ---------------------------------------------- no-allocation scratch
 // Device memory of lloid_orthonormalize_noalloc: the Gram matrix / Cholesky
-// factor (at most kNoAllocMaxBasis^2 doubles) followed by the two
-// breakdown flags used when the caller passes no flag buffer.  One copy per
+// factor and its inverse (at most kNoAllocMaxBasis^2 doubles each) followed
+// by the two breakdown flags used when the caller passes no flag buffer.  One copy per
 // GPU, held until the process ends; every call on a GPU shares it, so calls
 // that overlap on one GPU race.  Host code must use the address from
 // hipGetSymbolAddress (per device), never the array's name.
@@ -319,7 +319,7 @@ constexpr int kNoAllocMaxBasis = kMaxBasis;
 constexpr int64_t kScratchGramDoubles = (int64_t)kNoAllocMaxBasis * kNoAllocMaxBasis;
 constexpr int kMaxDevices = 64;
 }  // namespace
-static __device__ __align__(256) double scratch[kScratchGramDoubles + 32];
+static __device__ __align__(256) double scratch[2 * kScratchGramDoubles + 32];
 
 namespace {
 std::mutex g_scratch_mutex;
@@ -1444,14 +1444,14 @@ lloid_status lloid_orthonormalize(double *U, int32_t L, int32_t N, double *W, in
     hipStream_t st = static_cast<hipStream_t>(stream);
     double *G = nullptr;
     int32_t *info = nullptr;
-    if (hipMalloc(&G, sizeof(double) * L * L) != hipSuccess) return LLOID_E_NOMEM;
+    if (hipMalloc(&G, sizeof(double) * 2 * L * L) != hipSuccess) return LLOID_E_NOMEM;   // G, then C^-1
     if (hipMalloc(&info, sizeof(int32_t) * 2) != hipSuccess) {
         (void)hipFree(G);
         return LLOID_E_NOMEM;
     }
     int32_t h[2] = {0, 0};
     hipError_t e = launch_clear_info(st, info, 2);
-    if (e == hipSuccess) e = launch_cholesky_qr2(st, U, L, N, W, rows, G, info);
+    if (e == hipSuccess) e = launch_cholesky_qr2(st, U, L, N, W, rows, G, G + L * L, info);
     if (e == hipSuccess) e = hipMemcpyAsync(h, info, sizeof(h), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     (void)hipFree(G);
@@ -1466,11 +1466,11 @@ lloid_status lloid_orthonormalize_noalloc(double *U, int32_t L, int32_t N, doubl
     if (L > kNoAllocMaxBasis) return LLOID_E_UNSUPPORTED;   // the Gram matrix would not fit the scratch array
     double *base = nullptr;
     if (scratch_address(&base) != hipSuccess) return LLOID_E_HIP;
-    double *G = base;
-    int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(base + kScratchGramDoubles);
+    double *G = base, *Cinv = base + kScratchGramDoubles;
+    int32_t *info = info_dev ? info_dev : reinterpret_cast<int32_t *>(base + 2 * kScratchGramDoubles);
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipError_t e = launch_clear_info(st, info, 2);
-    if (e == hipSuccess) e = launch_cholesky_qr2(st, U, L, N, W, rows, G, info);
+    if (e == hipSuccess) e = launch_cholesky_qr2(st, U, L, N, W, rows, G, Cinv, info);
     return e == hipSuccess ? LLOID_OK : LLOID_E_HIP;
 }
 

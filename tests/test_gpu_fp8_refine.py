@@ -68,3 +68,46 @@ def test_quantisation_aware_refinement(lib, problem):  # noqa: F811
     before, after = _fp8_loss(lib, bank, x, target, T), _fp8_loss(lib, refined, x, target, T)
     print(f"FP8 plan loss: SVD bank {before:.4e}, refined {after:.4e}")
     assert after < before
+
+
+def test_fp8_refinement_on_the_realistic_bank(lib):
+    """The realistic bank (1024 templates, 5 rates, L = 40..120) in the FP8
+    form, before and after refining its mixing rows at the FP8 basis values
+    (20 steps over the first 72 s of strain, so that every slice, the
+    16-64 s one included, sees strain; target = the FP32 output of the
+    unrounded bank): the SNR error of the FP8 plan against the FP64 oracle of
+    the unrounded bank, at a steady-state stride past the refinement segment,
+    drops."""
+    from lloid_check import snr_error
+    from paper_2511_04730_amd.refine import refine
+    c2 = synth.cached_workload("c2", synth.config2)
+    bank, Fr = c2.banks[0], c2.sample_rate
+    T, k = 72, 80
+    x = synth.workload_strain(c2, k + 1)
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    seg = xs[:, :T * Fr].contiguous()
+    # the refinement filters its segment from zero history; the target is the
+    # unrounded bank's FP32 output over the same zero-history segment
+    ref = lib.LloidPlan([bank], Fr, 1, "fp32", normalize=False)
+    tg = torch.empty((T, ref.series_floats), dtype=torch.float32, device="cuda")
+    for i in range(T):
+        ref.push(seg[:, i * Fr:(i + 1) * Fr].contiguous(), series=tg[i])
+    ref.close()
+    plan = lib.LloidPlan([bank], Fr, 1, "fp32", normalize=False)
+    losses, U, W = refine(plan, [bank], seg, tg, steps=20, eta=0.25, quantize="fp8")
+    print(f"FP8-valued loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
+    assert all(b <= a * (1 + 1e-6) for a, b in zip(losses, losses[1:])) and losses[-1] < losses[0]
+    refined = synth.Bank(bank.n_templates, [synth.Slice(s.rate, s.delay, u.cpu().numpy(), w.cpu().numpy())
+                                            for s, u, w in zip(bank.slices, U, W)])
+    zr, _ = O.lloid_filter(x[0], bank, O.OracleConfig(Fr, normalize=False), n_strides=1, first_stride=k)
+    eps = {}
+    for name, b in (("before", bank), ("after", refined)):
+        p8 = lib.LloidPlan([b], Fr, 1, "fp8_bf16", normalize=False)
+        for i in range(k + 1):
+            z, _ = p8.push(xs[:, i * Fr:(i + 1) * Fr].contiguous())
+        zg = p8.bank_view(z, 0).cpu().numpy().astype(np.complex128)[0]
+        eps[name] = (snr_error(zg, zr), float(np.sqrt(np.mean(np.abs(zg - zr) ** 2) / np.mean(np.abs(zr) ** 2))))
+        p8.close()
+    print(f"FP8 form vs FP64 oracle of the unrounded bank: eps {eps['before'][0]:.3e} -> {eps['after'][0]:.3e}, "
+          f"rel rms {eps['before'][1]:.3e} -> {eps['after'][1]:.3e}", flush=True)
+    assert eps["after"][1] < eps["before"][1]

@@ -1,12 +1,16 @@
 """GPU SVD bank construction (Sec. II.C.1) through the C ABI against the
-oracle's truncated SVD: the rank-L reconstruction W U (unique when
-sigma_L > sigma_{L+1}) element by element, orthonormal basis rows, and the
-filter the GPU-built slice gives."""
+oracle's truncated SVD.  Where the spectrum has a gap (sigma_L > sigma_{L+1})
+the rank-L reconstruction W U is unique and is compared element by element;
+where it has none (the realistic chirp bank's slices) the truncation is not
+unique, and the GPU basis is checked for near-optimal captured energy against
+the oracle's singular values (Eckart-Young: no rank-L basis captures more),
+with its filter output against the oracle filtering the same GPU-built bank."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import lloid as O
+from lloid_check import snr_error
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -20,6 +24,20 @@ def lib():
     return P
 
 
+def _iters(sv, L, tol=1e-14):
+    ratio = sv[L] / sv[L - 1]
+    return int(np.ceil(np.log(tol) / (2 * np.log(ratio)))) + 20
+
+
+def _check_unique(H, L, U, W):
+    Uo, Wo = O.svd_truncate(H, L)
+    err = np.abs(W @ U - Wo @ Uo).max() / np.abs(H).max()
+    print(f"L={L}: reconstruction difference {err:.2e}", flush=True)
+    assert err < 1e-9
+    assert np.abs(U @ U.T - np.eye(L)).max() < 1e-12
+    assert np.abs(W - H @ U.T).max() < 1e-12 * np.abs(H).max()
+
+
 @pytest.mark.parametrize("L", [4, 12])
 def test_svd_basis_matches_oracle(lib, L):
     from paper_2511_04730_amd.plan import svd_basis
@@ -27,19 +45,79 @@ def test_svd_basis_matches_oracle(lib, L):
                             keep_templates=True)
     H = np.asarray(bank.templates[0], np.float64)                 # [20, 300]
     sv = np.linalg.svd(H, compute_uv=False)
-    ratio = sv[L] / sv[L - 1]
-    iters = int(np.ceil(np.log(1e-14) / (2 * np.log(ratio)))) + 20
-    print(f"L={L}: sigma ratio {ratio:.3f}, {iters} iterations")
+    iters = _iters(sv, L)
     g = synth.rng_for(88, synth.PURPOSE_NOISE, 1)
     start = torch.from_numpy(g.standard_normal((L, H.shape[1]))).cuda()
     U, W = svd_basis(torch.from_numpy(H).cuda(), L, start, iters=iters)
-    U, W = U.cpu().numpy(), W.cpu().numpy()
-    Uo, Wo = O.svd_truncate(H, L)
-    err = np.abs(W @ U - Wo @ Uo).max() / np.abs(H).max()
-    print(f"reconstruction difference {err:.2e}")
-    assert err < 1e-9
-    assert np.abs(U @ U.T - np.eye(L)).max() < 1e-12
-    assert np.abs(W - H @ U.T).max() < 1e-12 * np.abs(H).max()
+    _check_unique(H, L, U.cpu().numpy(), W.cpu().numpy())
+
+
+@pytest.mark.parametrize("L, N", [(40, 1024), (120, 1536), (160, 1111)])
+def test_svd_basis_with_a_spectral_gap(lib, L, N):
+    """2048 rows: the benchmark's shape at L = 40 and ranks past the in-LDS
+    Cholesky (L > 88) up to the limit of 160, on a seeded matrix whose
+    spectrum decays as 0.97^k with a factor 0.7 drop after index L (so the
+    truncation is unique), and a tap count that is no multiple of 64."""
+    from paper_2511_04730_amd.plan import svd_basis
+    rows = 2048
+    g = np.random.default_rng([88, 2, L])
+    k = 2 * L
+    A = np.linalg.qr(g.standard_normal((rows, k)))[0]
+    B = np.linalg.qr(g.standard_normal((N, k)))[0]
+    sv = 0.97 ** np.arange(k) * np.where(np.arange(k) < L, 1.0, 0.7)
+    H = (A * sv) @ B.T
+    start = torch.from_numpy(g.standard_normal((L, N))).cuda()
+    U, W = svd_basis(torch.from_numpy(H).cuda(), L, start, iters=_iters(sv, L))
+    _check_unique(H, L, U.cpu().numpy(), W.cpu().numpy())
+
+
+def test_realistic_bank_built_on_the_gpu(lib):
+    """The realistic bank (1024 chirps, 5 slices of 1024..12288 taps,
+    L = 40/60/80/100/120) truncated on the GPU from its slice template
+    matrices: every slice's basis is orthonormal, W = H U^T, and the energy
+    it captures is within 3e-4 of the optimum sum_{l<L} sigma_l^2 after 100
+    iterations (these slices have sigma_{L+1} / sigma_L up to 0.9994, so the
+    basis itself is not unique and converges slowly: the same iteration in
+    NumPy leaves 4e-5 .. 1.1e-4); a plan holding the GPU-built bank filters like the oracle
+    filtering that same bank (FP32, 1e-5), and its SNR differs from the
+    oracle's truncated-SVD bank by no more than the two banks' truncation
+    residuals allow."""
+    from paper_2511_04730_amd.plan import svd_basis
+    bank = synth.config2(duration_s=66, keep_templates=True).banks[0]
+    built = []
+    for i, (s, H) in enumerate(zip(bank.slices, bank.templates)):
+        L = s.n_basis
+        g = synth.rng_for(2, synth.PURPOSE_NOISE, 100 + i)
+        start = torch.from_numpy(g.standard_normal((L, H.shape[1]))).cuda()
+        Ht = torch.from_numpy(np.ascontiguousarray(H)).cuda()
+        U, W = svd_basis(Ht, L, start, iters=100)
+        U, W = U.cpu().numpy(), W.cpu().numpy()
+        sv = np.linalg.svd(H, compute_uv=False)
+        best = float(np.sum(sv[:L] ** 2))
+        got = float(np.sum((W @ U) ** 2))
+        print(f"slice {i} ({s.rate} Hz, N {s.n_taps}, L {L}): captured {got / best:.8f} of the optimum, "
+              f"sigma ratio {sv[L] / sv[L - 1]:.4f}", flush=True)
+        assert np.abs(U @ U.T - np.eye(L)).max() < 1e-12
+        assert np.abs(W - H @ U.T).max() < 1e-11 * np.abs(H).max()
+        assert got <= best * (1 + 1e-12) and got >= best * (1 - 3e-4)
+        built.append(synth.Slice(s.rate, s.delay, U, W))
+    gpu_bank = synth.Bank(bank.n_templates, built)
+    F, k = 4096, 65
+    x = synth.gaussian_strain(2, 1, (k + 1) * F)
+    plan = lib.LloidPlan([gpu_bank], F, 1, "fp32")
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    for i in range(k + 1):
+        z, _ = plan.push(xs[:, i * F:(i + 1) * F].contiguous())
+    zg = plan.bank_view(z, 0).cpu().numpy().astype(np.complex128)[0]
+    cfg = O.OracleConfig(F)
+    z_same, _ = O.lloid_filter(x[0], gpu_bank, cfg, n_strides=1, first_stride=k)
+    eps = snr_error(zg, z_same)
+    print(f"GPU-built bank: GPU filter vs oracle filter of the same bank, eps = {eps:.3e}", flush=True)
+    assert eps <= 1e-5
+    z_svd, _ = O.lloid_filter(x[0], bank, cfg, n_strides=1, first_stride=k)
+    d = np.sqrt(np.mean(np.abs(z_same - z_svd) ** 2) / np.mean(np.abs(z_svd) ** 2))
+    print(f"GPU-built bank vs the oracle's truncated-SVD bank: rel rms SNR difference {d:.3e}", flush=True)
+    assert d < 0.5
 
 
 def test_rank_deficient_start_is_an_error(lib):
