@@ -262,21 +262,27 @@ hipError_t launch_peaks(const LaunchCtx &ctx, const PeakItem *items, int32_t n_i
 
 // --------------------------------------------------- plan-time conversion
 // Per real row r: inv[r] = 1 / sqrt(sum_s sum_l W^s[r,l]^2) in FP64 (or 1).
+// One wave per row: the lanes stride over the row's basis coefficients of
+// every slice (consecutive lanes read consecutive doubles), then a fixed
+// butterfly sums the 64 partial sums.
 __global__ void normalize_kernel(const double *const *__restrict__ W64, const int32_t *__restrict__ Ls,
                                  int32_t n_slices, int32_t rows, int32_t normalize, double *__restrict__ inv) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= rows) return;
+    const int r = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= rows) return;   // wave-uniform
     double s = 0.0;
     for (int i = 0; i < n_slices; ++i) {
         const double *w = W64[i] + (int64_t)r * Ls[i];
-        for (int l = 0; l < Ls[i]; ++l) s = fma(w[l], w[l], s);
+        for (int l = lane; l < Ls[i]; l += 64) s = fma(w[l], w[l], s);
     }
-    inv[r] = (normalize && s > 0.0) ? 1.0 / sqrt(s) : 1.0;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (lane == 0) inv[r] = (normalize && s > 0.0) ? 1.0 / sqrt(s) : 1.0;
 }
 
 hipError_t launch_normalize(hipStream_t st, const double *const *W64, const int32_t *Ls, int32_t n_slices,
                             int32_t rows, int32_t normalize, double *inv_norm) {
-    hipLaunchKernelGGL(normalize_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, W64, Ls, n_slices, rows,
+    hipLaunchKernelGGL(normalize_kernel, dim3((rows + 3) / 4), dim3(256), 0, st, W64, Ls, n_slices, rows,
                        normalize, inv_norm);
     return hipGetLastError();
 }
