@@ -433,7 +433,8 @@ lloid_status lloid_whitener_psd(lloid_whitener *whitener, float *psd_dev, void *
  *   U_dev  device float64 [L][N]: in, the starting rows (for instance
  *          seeded Gaussian); out, the orthonormal basis
  *   W_dev  device float64 [rows][L]: out, H U^T
- * 1 <= L <= min(160, rows, N).  Synchronises `stream`.
+ * 1 <= L <= min(160, rows, N) and rows N < 2^28 (H under 2 GiB: the
+ * products address it with 32-bit byte offsets).  Synchronises `stream`.
  * Errors: LLOID_E_ARG, LLOID_E_NOMEM, LLOID_E_STATE (the iterated rows
  * became linearly dependent: a start without components in the subspace,
  * or a rank of H below L), LLOID_E_HIP. */

@@ -185,8 +185,6 @@ hipError_t launch_sum_parts(hipStream_t, const float *part, int32_t nsplit, int6
                             int32_t accumulate);
 hipError_t launch_cholesky_qr2(hipStream_t, double *U, int32_t L, int32_t N, double *W, int32_t rows,
                                double *G, double *Cinv, int32_t *info);
-hipError_t launch_cholesky_qr(hipStream_t, double *U, int32_t L, int32_t N, double *W, int32_t rows, double *G,
-                              double *Cinv, int32_t *info, int passes);
 hipError_t launch_clear_info(hipStream_t, int32_t *info, int32_t n);
 hipError_t launch_normalize(hipStream_t, const double *const *W64, const int32_t *Ls,
                             int32_t n_slices, int32_t rows, int32_t normalize, double *inv_norm);

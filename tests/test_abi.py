@@ -117,3 +117,19 @@ def test_noalloc_orthonormalize_host_checks(L):
     assert lib.lloid_orthonormalize_noalloc(fake, 0, 100, fake, 10, None, None) == -1
     assert lib.lloid_orthonormalize_noalloc(fake, 8, 7, fake, 10, None, None) == -1
     assert lib.lloid_orthonormalize_noalloc(fake, 161, 400, fake, 10, None, None) == -7
+
+
+def test_svd_basis_host_checks(L):
+    """The SVD construction rejects bad sizes on the host before any device
+    work: NULL buffers, L outside 1 .. min(160, rows, N), no iterations, and a
+    template matrix of 2^28 doubles or more (its products address it with
+    32-bit byte offsets), all with LLOID_E_ARG."""
+    lib = L.load()
+    fake = ctypes.c_void_p(0x1000)      # never dereferenced: rejected first
+    assert lib.lloid_svd_basis(None, 64, 128, 8, 4, fake, fake, None) == -1
+    assert lib.lloid_svd_basis(fake, 64, 128, 8, 4, None, fake, None) == -1
+    assert lib.lloid_svd_basis(fake, 64, 128, 0, 4, fake, fake, None) == -1
+    assert lib.lloid_svd_basis(fake, 64, 128, 65, 4, fake, fake, None) == -1
+    assert lib.lloid_svd_basis(fake, 200, 400, 161, 4, fake, fake, None) == -1
+    assert lib.lloid_svd_basis(fake, 64, 128, 8, 0, fake, fake, None) == -1
+    assert lib.lloid_svd_basis(fake, 1 << 14, 1 << 14, 8, 4, fake, fake, None) == -1
