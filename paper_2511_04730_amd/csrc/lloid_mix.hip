@@ -173,9 +173,9 @@ struct MixF32 {
         for (int t = 0; t < 6; ++t) k.b[t] = ker_value(4 * t + lg, u.off, u.ph, nup, taps);
         return k;
     }
-    static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, int logp,
-                                                    const KerF &k, int li, int lg, floatx4 (&acc)[kRB]) {
-        (void)logp;
+    template <bool P2>
+    static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, const KerF &k,
+                                                    int li, int lg, floatx4 (&acc)[kRB]) {
         const float *prev = static_cast<const float *>(lvl) + rw * kMixS;
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
@@ -193,9 +193,10 @@ struct MixF32 {
 template <typename T, typename T8, bool SPLIT_W>
 struct Mix16 {
     static constexpr int K = 32;
-    static constexpr bool STAGED = true;   // y through LDS stages, W~ one chunk ahead
+    static constexpr bool STAGED = true;   // y through LDS stages, W~ in registers ahead of the MFMAs
     static constexpr int PLANES = 2;       // ring planes: hi, lo
     static constexpr int RING_G = 8;       // ring outputs per 16-byte group
+    static constexpr int A_LOADS = kRB * (SPLIT_W ? 2 : 1);   // W~ loads per wave and chunk
     struct ASrc {
         __amdgpu_buffer_rsrc_t wh, wl;
         int va0;       // per lane: row block 0 of this wave, lane group's K offset
@@ -265,40 +266,47 @@ struct Mix16 {
         }
         return k;
     }
-    static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, int logp,
-                                                    const KerF &k, int li, int lg, floatx4 (&acc)[kRB]) {
+    // p = 2: m0 = 8 cb, so every window read is 16-byte aligned
+    template <bool P2>
+    static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, const KerF &k,
+                                                    int li, int lg, floatx4 (&acc)[kRB]) {
+        static_assert(P2, "16-bit fragment reads need p = 2");
         (void)n_prev;
         const T *hi = static_cast<const T *>(lvl);
         const int e = m0 + 8 * min(lg, 2);
 #pragma unroll
         for (int m = 0; m < kRB; ++m) {
             const T *ph = hi + (rw + 16 * m + li) * SB + e;
-            const T *pl = ph + kMixTM * SB;
-            T8 ah, al;
-            if (logp == 1) {   // m0 = 8 cb: 16-byte aligned
-                ah = *reinterpret_cast<const T8 *>(ph);
-                al = *reinterpret_cast<const T8 *>(pl);
-            } else if (logp == 2) {   // m0 = 4 cb: 8-byte aligned
-                typedef T T4 __attribute__((ext_vector_type(4)));
-                const T4 h0 = *reinterpret_cast<const T4 *>(ph), h1 = *reinterpret_cast<const T4 *>(ph + 4);
-                const T4 l0 = *reinterpret_cast<const T4 *>(pl), l1 = *reinterpret_cast<const T4 *>(pl + 4);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    ah[j] = h0[j];
-                    ah[j + 4] = h1[j];
-                    al[j] = l0[j];
-                    al[j + 4] = l1[j];
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    ah[j] = ph[j];
-                    al[j] = pl[j];
-                }
-            }
+            const T8 ah = *reinterpret_cast<const T8 *>(ph);
+            const T8 al = *reinterpret_cast<const T8 *>(ph + kMixTM * SB);
             acc[m] = mfma16(ah, k.l, acc[m]);
             acc[m] = mfma16(al, k.h, acc[m]);
             acc[m] = mfma16(ah, k.h, acc[m]);
+        }
+    }
+    // any other ratio: a 24-wide window in six FP32 16x16x4 steps (as the
+    // FP32 form), each level value read as hi + lo; lane group g holds
+    // Ker[4t + g][c]
+    struct KerF32 {
+        float b[6];
+    };
+    static __device__ __forceinline__ KerF32 ker32(UpPos u, int nup, const float *taps, int lg) {
+        KerF32 k;
+#pragma unroll
+        for (int t = 0; t < 6; ++t) k.b[t] = ker_value(4 * t + lg, u.off, u.ph, nup, taps);
+        return k;
+    }
+    static __device__ __forceinline__ void upsample32(const void *lvl, int rw, int m0, int n_prev, const KerF32 &k,
+                                                      int li, int lg, floatx4 (&acc)[kRB]) {
+        const T *hi = static_cast<const T *>(lvl);
+#pragma unroll
+        for (int t = 0; t < 6; ++t) {
+            const int idx = min(m0 + 4 * t + lg, n_prev - 1);
+#pragma unroll
+            for (int m = 0; m < kRB; ++m) {
+                const int o = (rw + 16 * m + li) * SB + idx;
+                acc[m] = mfma_16x16x4_f32((float)hi[o] + (float)hi[kMixTM * SB + o], k.b[t], acc[m]);
+            }
         }
     }
 };
@@ -317,6 +325,28 @@ struct StageSrc {
 };
 
 // ------------------------------------------------------------------ kernel
+template <int V>
+struct IntC {
+    static constexpr int value = V;
+};
+// The lower levels' windows are at most kMixS columns: at most kCBL column
+// blocks per wave, so their accumulators take 80 registers instead of 128
+// and a third pipeline stage fits (below).
+constexpr int kCBL = ((kMixS + 15) / 16 + kWC - 1) / kWC;
+static_assert(kCBL <= kCB, "lower-level accumulators");
+// three lower-level stages (both planes, four K groups, the staged columns
+// rounded up to 64) fit the level buffer
+constexpr int kLowStageBytes = 2 * 4 * (((kMixS + 15) / 16 * 16 + 63) / 64) * 1024;
+static_assert(3 * kLowStageBytes <= Mix16<__bf16, bf16x8, true>::LVL_BYTES, "three lower-level stages");
+
+// s_waitcnt vmcnt(N) (gfx9 encoding: low four bits and bits 15:14; the LDS
+// and export counters left at their maxima)
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+    static_assert(N >= 0 && N < 64, "vmcnt");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+}
+
 template <typename Op>
 __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__ items, const MixBank *__restrict__ banks,
                                                   const MixSlice *__restrict__ slices,
@@ -350,61 +380,168 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
     for (int e = tid; e < Op::LVL_BYTES / 16; e += 256) reinterpret_cast<uint4 *>(lds)[e] = uint4{0, 0, 0, 0};
 
     int lo_prev = 0;
-    for (int j = B.nlev - 1; j >= 0; --j) {
-        const int lo = B.lo[j] + (it.t0 >> B.shP[j]);
-        const int n = B.n[j];
-        const int nb = (n + 15) >> 4;
-        floatx4 acc[kCB][kRB];
-#pragma unroll
-        for (int i = 0; i < kCB; ++i)
-#pragma unroll
-            for (int m = 0; m < kRB; ++m) acc[i][m] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-        // this wave's column blocks cb = wc + kWC i, i < ncb
-        const int ncb = min(kCB, max(0, (nb - wc + kWC - 1) / kWC));
-        // acc += H_up(level j+1), read from the LDS level buffer
-        auto upsample_level = [&]() {
-            if (j < B.nlev - 1) {
-                const int logp = B.shp[j + 1];
-                const float *taps = tp + B.up_off[j + 1];
-                const int n_prev = B.n[j + 1];
-                // for p <= 16 one kernel fragment serves every block of the level
+    // acc += H_up(level j + 1), read from the LDS level buffer (levels below
+    // the lowest); acc has NC column blocks cb = wc + kWC i.  Ratio p = 2 (the
+    // usual octave step) takes aligned window reads and one kernel fragment
+    // for every block of the level (block starts are multiples of 16 past the
+    // window start); any other ratio takes element reads (hi + lo) into
+    // FP32 products and the fragment of each block.  The FP32 form reads
+    // elements at every ratio and shares the fragment for p <= 16.
+    auto upsample_level = [&](int j, int lo, int nb, auto &acc) {
+        constexpr int NC = sizeof(acc) / sizeof(acc[0]);
+        if (j < B.nlev - 1) {
+            const int logp = B.shp[j + 1];
+            const float *taps = tp + B.up_off[j + 1];
+            const int n_prev = B.n[j + 1];
+            if constexpr (!Op::STAGED) {
+                // FP32: one loop, the shared fragment for p <= 16
                 const typename Op::KerF k0 = Op::ker(up_pos(lo, li, logp), nup, taps, lg);
 #pragma unroll
-                for (int i = 0; i < kCB; ++i) {
+                for (int i = 0; i < NC; ++i) {
                     const int cb = wc + kWC * i;
                     if (cb >= nb) continue;   // wave-uniform
                     const int i0 = lo + cb * 16;
                     const int m0 = (i0 >> logp) - nup - lo_prev;
                     if (logp <= 4) {
-                        Op::upsample(lvl, rw, m0, n_prev, logp, k0, li, lg, acc[i]);
+                        Op::template upsample<false>(lvl, rw, m0, n_prev, k0, li, lg, acc[i]);
                     } else {
                         const typename Op::KerF kb = Op::ker(up_pos(i0, li, logp), nup, taps, lg);
-                        Op::upsample(lvl, rw, m0, n_prev, logp, kb, li, lg, acc[i]);
+                        Op::template upsample<false>(lvl, rw, m0, n_prev, kb, li, lg, acc[i]);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            } else if (logp == 1) {
+                const typename Op::KerF k0 = Op::ker(up_pos(lo, li, 1), nup, taps, lg);
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    const int cb = wc + kWC * i;
+                    if (cb >= nb) continue;   // wave-uniform
+                    const int m0 = ((lo + cb * 16) >> 1) - nup - lo_prev;
+                    Op::template upsample<true>(lvl, rw, m0, n_prev, k0, li, lg, acc[i]);
                     __builtin_amdgcn_sched_barrier(0);   // keep one block's LDS reads in flight at a time
                 }
+            } else {
+                // a rolled loop over the blocks (this path is rare: one copy
+                // of its element reads instead of one per block); each block's
+                // tile goes to its accumulators, still zero at this point, so
+                // the sum is exact
+                const int ncb = min(NC, max(0, (nb - wc + kWC - 1) / kWC));
+#pragma unroll 1
+                for (int i = 0; i < ncb; ++i) {
+                    const int i0 = lo + (wc + kWC * i) * 16;
+                    const int m0 = (i0 >> logp) - nup - lo_prev;
+                    const auto kb = Op::ker32(up_pos(i0, li, logp), nup, taps, lg);
+                    floatx4 t[kRB];
+#pragma unroll
+                    for (int m = 0; m < kRB; ++m) t[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Op::upsample32(lvl, rw, m0, n_prev, kb, li, lg, t);
+#pragma unroll
+                    for (int q = 0; q < NC; ++q)
+                        if (q == i)   // wave-uniform
+#pragma unroll
+                            for (int m = 0; m < kRB; ++m) acc[q][m] += t[m];
+                }
             }
-        };
-        if constexpr (Op::STAGED) {
-            upsample_level();
-            __syncthreads();   // every wave is done reading level j+1: the buffer now stages y
+        }
+    };
 
-            // contraction over the chunks (slice s, basis rows l0 .. l0 + K) of
-            // level j.  Each chunk's y window (ncs columns, every group of the K
-            // rows, both planes) is copied by the work group from the ring into
-            // one of two LDS stages with asynchronous buffer-to-LDS loads, and
-            // each wave's W~ fragments are loaded into registers, one chunk ahead:
-            // per chunk one wait and one barrier, then the next chunk's copies
-            // and W~ loads go out before this chunk's MFMAs.
+    // level j >= 1: acc goes to the LDS level buffer for the next level up
+    auto write_level = [&](int n, int nb, const auto &acc) {
+        constexpr int NC = sizeof(acc) / sizeof(acc[0]);
+#pragma unroll
+        for (int i = 0; i < NC; ++i) {
+            const int cb = wc + kWC * i;
+            if (cb >= nb) continue;
+            const int c = cb * 16 + li;
+            if (c >= n) continue;
+#pragma unroll
+            for (int m = 0; m < kRB; ++m)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Op::lvl_store(lvl, rw + 16 * m + 4 * lg + v, c, acc[i][m][v]);
+        }
+    };
+
+    // level 0: SNR series and trigger candidates.  Lane (li, lg) holds
+    // templates t8 + 8 m + h, t8 = (r0 + rw)/2 + 2 lg, at the samples
+    // t0 + cb 16 + li; one template's candidate is live at a time.
+    auto epilogue = [&](int n, int nb, const auto &acc) {
+        constexpr int NC = sizeof(acc) / sizeof(acc[0]);
+        const int t8 = (it.r0 + rw) / 2 + 2 * lg;
+        float2 *orow = series ? reinterpret_cast<float2 *>(series + B.series_off) +
+                                    ((int64_t)it.det * B.M + t8) * F + it.t0 + li
+                              : nullptr;
+#pragma unroll
+        for (int m = 0; m < kRB; ++m) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool live = t8 + 8 * m + h < B.M;
+                PeakCand b{-1.0f, 0x7fffffff, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < NC; ++i) {
+                    const int cb = wc + kWC * i;
+                    if (cb >= nb) continue;
+                    const int c = cb * 16 + li;
+                    if (c >= n) continue;
+                    const float re = acc[i][m][2 * h], im = acc[i][m][2 * h + 1];
+                    // streamed past the caches: the series is never re-read by this
+                    // launch and would otherwise evict W~ and the basis outputs
+                    if (orow && live)
+                        __builtin_nontemporal_store(f32x2{re, im},
+                                                    reinterpret_cast<f32x2 *>(orow + (int64_t)(8 * m + h) * F + cb * 16));
+                    const float p2 = re * re + im * im;
+                    if (better(p2, it.t0 + c, b.p2, b.idx)) b = PeakCand{p2, it.t0 + c, re, im};
+                }
+                // reduce over the 16 lanes of the row group: pairs, quads,
+                // half rows, rows (the order is total, so any butterfly gives
+                // the same candidate)
+                reduce_dpp<0xB1>(b);    // quad_perm 1, 0, 3, 2
+                reduce_dpp<0x4E>(b);    // quad_perm 2, 3, 0, 1
+                reduce_dpp<0x141>(b);   // row_half_mirror
+                reduce_dpp<0x140>(b);   // row_mirror
+                if (li == 0) wbest[wave][8 * m + 2 * lg + h] = b;
+            }
+        }
+    };
+
+    if constexpr (Op::STAGED) {
+        // One level of the 16-bit forms: upsampled level j + 1 into the
+        // accumulators, then the contraction over the chunks (slice s, basis
+        // rows l0 .. l0 + K) of level j.  Each chunk's y window (ncs columns,
+        // every group of the K rows, both planes) is copied by the work group
+        // from the ring into one of DEPTH LDS stages (in the level buffer,
+        // free while a level contracts) with asynchronous buffer-to-LDS loads,
+        // and each wave's W~ fragments are loaded into one of DEPTH register
+        // sets, DEPTH - 1 chunks ahead of the MFMAs: per chunk one wait (for
+        // that chunk's loads only) and one barrier, then the loads of chunk
+        // c + DEPTH - 1 go out (into the stage and registers chunk c - 1 used)
+        // before chunk c's MFMAs.  The top level runs two stages (a 256-column
+        // stage is 32 KB); the lower levels, whose windows stage at most 192
+        // columns (24 KB), run three, so that their short chunks overlap two
+        // chunks' load latency instead of one.
+        auto staged_level = [&](int j, auto ncb_c, auto depth_c, auto top_c) {
+            constexpr int NC = decltype(ncb_c)::value;
+            constexpr int DEPTH = decltype(depth_c)::value;
+            constexpr bool TOP = decltype(top_c)::value;   // level 0
+            const int lo = B.lo[j] + (it.t0 >> B.shP[j]);
+            const int n = B.n[j];
+            const int nb = (n + 15) >> 4;
+            floatx4 acc[NC][kRB];
+#pragma unroll
+            for (int i = 0; i < NC; ++i)
+#pragma unroll
+                for (int m = 0; m < kRB; ++m) acc[i][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // this wave's column blocks cb = wc + kWC i, i < ncb
+            const int ncb = min(NC, max(0, (nb - wc + kWC - 1) / kWC));
+            upsample_level(j, lo, nb, acc);
+            __syncthreads();   // every wave is done reading level j+1: the buffer now stages y
             {
                 const int sb = B.slice_begin[j], se = B.slice_begin[j + 1];
                 const int ncs = min(kMixTN, (nb * 16 + 63) & ~63);   // staged columns
                 const int nq = ncs >> 6;                             // 64-column copies per plane and group
-                const int ncopy = Op::PLANES * 4 * nq;
-                const int stage_bytes = ncopy * 1024;                // <= LVL_BYTES / 2
+                const int stage_bytes = Op::PLANES * 4 * nq * 1024;  // DEPTH stages fit LVL_BYTES
                 const uint32_t rate = (uint32_t)B.rate[j];
-                // Per slice (set up once when the contraction reaches it): the
+                // Per slice (set up once when the issue cursor reaches it): the
                 // ring's buffer resource and, per lane, the byte offset of each
                 // of its (up to four) 64-column copies.  Wave w copies K group
                 // w of every plane; the step over basis rows is the scalar
@@ -429,6 +566,7 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     c.Lpad = ms.Lpad;
                     Op::init_a(c.as, ms, it.r0 + rw, li, lg);
                 };
+                // per wave and chunk: nq copies per plane, then the W~ loads
                 auto issue = [&](const YCtx &c, int l0, int so, typename Op::FragA &fa) {
                     // the builtin's operands are plain locals: taken straight from
                     // the struct, the host pass drops the kernel's instantiation
@@ -449,46 +587,95 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     }
                     Op::load_a(fa, c.as, l0);
                 };
-                int cs = sb, cl = 0, so = 0;
-                YCtx yc;   // the slice of the last chunk issued
-                typename Op::FragA fa0, fa1;
-                if (sb < se) {
-                    prepare(sb, yc);
-                    issue(yc, 0, 0, fa0);
-                }
-                auto step = [&](const typename Op::FragA &fcur, typename Op::FragA &fnext) -> bool {
-                    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this chunk's copies and W~ have landed
-                    __syncthreads();                      // ... for every wave; the other stage is free
-                    int ns = cs, nl = cl + Op::K;
-                    bool more = true;
-                    if (nl >= yc.Lpad) {
-                        ++ns;
-                        nl = 0;
-                        more = ns < se;
-                        if (more) prepare(ns, yc);
-                    }
-                    if (more) issue(yc, nl, so ^ stage_bytes, fnext);
-                    const char *st = lds + so;
-#pragma unroll
-                    for (int i = 0; i < kCB; ++i) {
-                        if (i >= ncb) break;   // wave-uniform
-                        typename Op::FragB b;
-                        Op::read_b(b, st, ncs, wc + kWC * i, li, lg);
-                        Op::mma(acc[i], fcur, b);
-                    }
-                    cs = ns;
-                    cl = nl;
-                    so ^= stage_bytes;
-                    return more;
+                // wait until the chunk about to be used has landed, with
+                // `ahead` later chunks (0 or 1) still in flight: loads return
+                // in issue order, so the count allows exactly their loads
+                auto wait_chunk = [&](int ahead) {
+                    if (ahead == 0) wait_vmcnt<0>();
+                    else if (nq == 1) wait_vmcnt<2 * 1 + Op::A_LOADS>();
+                    else if (nq == 2) wait_vmcnt<2 * 2 + Op::A_LOADS>();
+                    else if (nq == 3) wait_vmcnt<2 * 3 + Op::A_LOADS>();
+                    else wait_vmcnt<2 * 4 + Op::A_LOADS>();
                 };
-                if (sb < se)
-                    for (;;) {
-                        if (!step(fa0, fa1)) break;
-                        if (!step(fa1, fa0)) break;
+                if (sb < se) {
+                    YCtx yc;   // the slice of the issue cursor
+                    int is = sb, il = 0, issued = 0;
+                    bool more = true;   // the cursor is at a chunk not yet issued
+                    prepare(sb, yc);
+                    auto advance = [&]() {
+                        il += Op::K;
+                        if (il >= yc.Lpad) {
+                            ++is;
+                            il = 0;
+                            more = is < se;
+                            if (more) prepare(is, yc);
+                        }
+                    };
+                    typename Op::FragA fa[DEPTH];
+#pragma unroll
+                    for (int p = 0; p < DEPTH - 1; ++p) {
+                        if (more) {
+                            issue(yc, il, p * stage_bytes, fa[p]);
+                            ++issued;
+                            advance();
+                        }
                     }
+                    // chunk c uses stage and register set u = c mod DEPTH; false
+                    // once every chunk is consumed (wave-uniform)
+                    int c = 0;
+                    auto step = [&](auto u_c) -> bool {
+                        constexpr int u = decltype(u_c)::value;
+                        if (c >= issued) return false;
+                        wait_chunk(issued - c - 1);
+                        __syncthreads();   // ... for every wave; stage (c - 1) mod DEPTH is free
+                        if (more) {
+                            constexpr int q = (u + DEPTH - 1) % DEPTH;
+                            issue(yc, il, q * stage_bytes, fa[q]);
+                            ++issued;
+                            advance();
+                        }
+                        const char *st = lds + u * stage_bytes;
+#pragma unroll
+                        for (int i = 0; i < NC; ++i) {
+                            if (i >= ncb) break;   // wave-uniform
+                            typename Op::FragB b;
+                            Op::read_b(b, st, ncs, wc + kWC * i, li, lg);
+                            Op::mma(acc[i], fa[u], b);
+                        }
+                        ++c;
+                        return true;
+                    };
+                    for (;;) {
+                        if (!step(IntC<0>{})) break;
+                        if (!step(IntC<1>{})) break;
+                        if constexpr (DEPTH > 2)
+                            if (!step(IntC<2>{})) break;
+                    }
+                }
             }
             __syncthreads();   // every wave is done reading the stages
-        } else {
+            if constexpr (!TOP) {
+                write_level(n, nb, acc);
+                __syncthreads();   // level j complete before it is read as prev
+                lo_prev = lo;
+            } else {
+                epilogue(n, nb, acc);
+            }
+        };
+        for (int j = B.nlev - 1; j >= 1; --j) staged_level(j, IntC<kCBL>{}, IntC<3>{}, IntC<0>{});
+        staged_level(0, IntC<kCB>{}, IntC<2>{}, IntC<1>{});
+    } else {
+        for (int j = B.nlev - 1; j >= 0; --j) {
+            const int lo = B.lo[j] + (it.t0 >> B.shP[j]);
+            const int n = B.n[j];
+            const int nb = (n + 15) >> 4;
+            floatx4 acc[kCB][kRB];
+#pragma unroll
+            for (int i = 0; i < kCB; ++i)
+#pragma unroll
+                for (int m = 0; m < kRB; ++m) acc[i][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // this wave's column blocks cb = wc + kWC i, i < ncb
+            const int ncb = min(kCB, max(0, (nb - wc + kWC - 1) / kWC));
             // direct-load contraction: both operands straight into registers
             for (int s = B.slice_begin[j]; s < B.slice_begin[j + 1]; ++s) {
                 const MixSlice &ms = slices[s];
@@ -516,61 +703,14 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     }
                 }
             }
-            upsample_level();
+            upsample_level(j, lo, nb, acc);
             __syncthreads();   // every wave is done reading level j+1
-        }
-        if (j > 0) {
-#pragma unroll
-            for (int i = 0; i < kCB; ++i) {
-                const int cb = wc + kWC * i;
-                if (cb >= nb) continue;
-                const int c = cb * 16 + li;
-                if (c >= n) continue;
-#pragma unroll
-                for (int m = 0; m < kRB; ++m)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) Op::lvl_store(lvl, rw + 16 * m + 4 * lg + v, c, acc[i][m][v]);
-            }
-            __syncthreads();   // level j complete before it is read as prev
-            lo_prev = lo;
-            continue;
-        }
-        // level 0: SNR series and trigger candidates.  Lane (li, lg) holds
-        // templates t8 + 8 m + h, t8 = (r0 + rw)/2 + 2 lg, at the samples
-        // t0 + cb 16 + li; one template's candidate is live at a time.
-        const int t8 = (it.r0 + rw) / 2 + 2 * lg;
-        float2 *orow = series ? reinterpret_cast<float2 *>(series + B.series_off) +
-                                    ((int64_t)it.det * B.M + t8) * F + it.t0 + li
-                              : nullptr;
-#pragma unroll
-        for (int m = 0; m < kRB; ++m) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const bool live = t8 + 8 * m + h < B.M;
-                PeakCand b{-1.0f, 0x7fffffff, 0.f, 0.f};
-#pragma unroll
-                for (int i = 0; i < kCB; ++i) {
-                    const int cb = wc + kWC * i;
-                    if (cb >= nb) continue;
-                    const int c = cb * 16 + li;
-                    if (c >= n) continue;
-                    const float re = acc[i][m][2 * h], im = acc[i][m][2 * h + 1];
-                    // streamed past the caches: the series is never re-read by this
-                    // launch and would otherwise evict W~ and the basis outputs
-                    if (orow && live)
-                        __builtin_nontemporal_store(f32x2{re, im},
-                                                    reinterpret_cast<f32x2 *>(orow + (int64_t)(8 * m + h) * F + cb * 16));
-                    const float p2 = re * re + im * im;
-                    if (better(p2, it.t0 + c, b.p2, b.idx)) b = PeakCand{p2, it.t0 + c, re, im};
-                }
-                // reduce over the 16 lanes of the row group: pairs, quads,
-                // half rows, rows (the order is total, so any butterfly gives
-                // the same candidate)
-                reduce_dpp<0xB1>(b);    // quad_perm 1, 0, 3, 2
-                reduce_dpp<0x4E>(b);    // quad_perm 2, 3, 0, 1
-                reduce_dpp<0x141>(b);   // row_half_mirror
-                reduce_dpp<0x140>(b);   // row_mirror
-                if (li == 0) wbest[wave][8 * m + 2 * lg + h] = b;
+            if (j > 0) {
+                write_level(n, nb, acc);
+                __syncthreads();   // level j complete before it is read as prev
+                lo_prev = lo;
+            } else {
+                epilogue(n, nb, acc);
             }
         }
     }
