@@ -154,9 +154,12 @@ struct Corr16 {
         T Dl[8 * DL];
     };
     static constexpr int PER = kCorrMB * 16 * (TK / 8) / 256;
+    // strain of a stage by sample pairs: pair p = tid + 256 i holds d[2p],
+    // d[2p + 1] and the next sample d[2p + 2]
+    static constexpr int NS = kCorrTQ + TK, NP = NS / 2, PPER = (NP + 255) / 256;
     struct Regs {
         u32x4 uh[PER], ul[SPLIT_U ? PER : 1];   // plain vector type: promoted to registers (HIP's uint4 is not)
-        StrainRegs<TK> d;
+        float d[PPER][3];
     };
     static __device__ __forceinline__ void gload(Regs &g, const CorrItem &it, int64_t p0, int kk, int tid) {
         const T *gh = static_cast<const T *>(it.Uhi);
@@ -171,7 +174,15 @@ struct Corr16 {
                 if constexpr (SPLIT_U) g.ul[i] = ld_global<u32x4>(gl + o);
             }
         }
-        g.d.load(it, p0, tid);
+        // samples past the item's columns + the stage's taps are never used: zeros
+        const int lim = min(NS, it.ncols + TK);
+#pragma unroll
+        for (int i = 0; i < PPER; ++i) {
+            const int e0 = 2 * (tid + 256 * i);
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+                g.d[i][q] = e0 + q < lim ? ld_global<float>(it.ring + p0 + e0 + q) : 0.0f;   // mirror ring
+        }
     }
     static __device__ __forceinline__ void lstore(const Regs &g, Smem &s, const CorrItem &it, int tid) {
 #pragma unroll
@@ -183,21 +194,33 @@ struct Corr16 {
                 if constexpr (SPLIT_U) *reinterpret_cast<u32x4 *>(&s.Ul[r * US + 8 * c8]) = g.ul[i];
             }
         }
-        // copy sft holds d[i + sft] at position i
+        // copy sft holds d[i + sft] at position i.  Pair p writes whole
+        // words: word p - s (positions 2p - 2s, + 1) of copy 2s is d[2p],
+        // d[2p + 1] and of copy 2s + 1 is d[2p + 1], d[2p + 2]; consecutive
+        // lanes write consecutive words (distinct banks)
+        typedef T T2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-        for (int k = 0; k < StrainRegs<TK>::PER; ++k) {
-            const int e = tid + 256 * k;
-            if (e >= StrainRegs<TK>::N) continue;
-            const float v = g.d.v[k];
-            const T h = (T)v;
-            const T l = (T)(v - (float)h);
+        for (int k = 0; k < PPER; ++k) {
+            const int p = tid + 256 * k;
+            if (p >= NP) continue;
+            T h[3], l[3];
 #pragma unroll
-            for (int sft = 0; sft < 8; ++sft) {
-                const int i = e - sft;
-                if (i >= 0) {
-                    s.Dh[sft * DL + i] = h;
-                    s.Dl[sft * DL + i] = l;
-                }
+            for (int q = 0; q < 3; ++q) {
+                h[q] = (T)g.d[k][q];
+                l[q] = (T)(g.d[k][q] - (float)h[q]);
+            }
+            const uint32_t he = __builtin_bit_cast(uint32_t, T2{h[0], h[1]});
+            const uint32_t le = __builtin_bit_cast(uint32_t, T2{l[0], l[1]});
+            const uint32_t ho = __builtin_bit_cast(uint32_t, T2{h[1], h[2]});
+            const uint32_t lo = __builtin_bit_cast(uint32_t, T2{l[1], l[2]});
+#pragma unroll
+            for (int sh = 0; sh < 4; ++sh) {
+                const int w = p - sh;
+                if (w < 0) continue;
+                *reinterpret_cast<uint32_t *>(&s.Dh[2 * sh * DL + 2 * w]) = he;
+                *reinterpret_cast<uint32_t *>(&s.Dl[2 * sh * DL + 2 * w]) = le;
+                *reinterpret_cast<uint32_t *>(&s.Dh[(2 * sh + 1) * DL + 2 * w]) = ho;
+                *reinterpret_cast<uint32_t *>(&s.Dl[(2 * sh + 1) * DL + 2 * w]) = lo;
             }
         }
     }
