@@ -173,9 +173,10 @@ struct MixF32 {
         for (int t = 0; t < 6; ++t) k.b[t] = ker_value(4 * t + lg, u.off, u.ph, nup, taps);
         return k;
     }
-    template <bool P2>
+    template <bool P2, int RB>
     static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, const KerF &k,
-                                                    int li, int lg, floatx4 (&acc)[kRB]) {
+                                                    int li, int lg, floatx4 (&acc)[RB]) {
+        static_assert(RB == kRB, "the FP32 form keeps the 2 x 2 wave layout");
         const float *prev = static_cast<const float *>(lvl) + rw * kMixS;
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
@@ -196,14 +197,17 @@ struct Mix16 {
     static constexpr bool STAGED = true;   // y through LDS stages, W~ in registers ahead of the MFMAs
     static constexpr int PLANES = 2;       // ring planes: hi, lo
     static constexpr int RING_G = 8;       // ring outputs per 16-byte group
-    static constexpr int A_LOADS = kRB * (SPLIT_W ? 2 : 1);   // W~ loads per wave and chunk
+    template <int RB>
+    static constexpr int a_loads = RB * (SPLIT_W ? 2 : 1);   // W~ loads per wave and chunk
     struct ASrc {
         __amdgpu_buffer_rsrc_t wh, wl;
         int va0;       // per lane: row block 0 of this wave, lane group's K offset
         int mstride;   // bytes from one 16-row block to the next (wave-uniform)
     };
+    // W~ fragments of RB 16-row blocks
+    template <int RB>
     struct FragA {
-        T8 h[kRB], l[SPLIT_W ? kRB : 1];
+        T8 h[RB], l[SPLIT_W ? RB : 1];
     };
     struct FragB {
         T8 h, l;
@@ -215,9 +219,10 @@ struct Mix16 {
         s.mstride = (ms.Lpad / 8) * 256;
         s.va0 = ((r0 >> 4) * (ms.Lpad / 8) + lg) * 256 + 16 * li;
     }
-    static __device__ __forceinline__ void load_a(FragA &f, const ASrc &s, int l0) {
+    template <int RB>
+    static __device__ __forceinline__ void load_a(FragA<RB> &f, const ASrc &s, int l0) {
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) {
+        for (int m = 0; m < RB; ++m) {
             f.h[m] = buffer_load16<T8>(s.wh, s.va0, l0 * 32 + m * s.mstride);
             if constexpr (SPLIT_W) f.l[m] = buffer_load16<T8>(s.wl, s.va0, l0 * 32 + m * s.mstride);
         }
@@ -228,9 +233,10 @@ struct Mix16 {
         f.h = *reinterpret_cast<const T8 *>(p);
         f.l = *reinterpret_cast<const T8 *>(p + 4 * ncs * 16);
     }
-    static __device__ __forceinline__ void mma(floatx4 (&acc)[kRB], const FragA &a, const FragB &f) {
+    template <int RB>
+    static __device__ __forceinline__ void mma(floatx4 (&acc)[RB], const FragA<RB> &a, const FragB &f) {
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) {
+        for (int m = 0; m < RB; ++m) {
             acc[m] = mfma16(a.h[m], f.l, acc[m]);
             if constexpr (SPLIT_W) acc[m] = mfma16(a.l[m], f.h, acc[m]);
             acc[m] = mfma16(a.h[m], f.h, acc[m]);
@@ -267,15 +273,15 @@ struct Mix16 {
         return k;
     }
     // p = 2: m0 = 8 cb, so every window read is 16-byte aligned
-    template <bool P2>
+    template <bool P2, int RB>
     static __device__ __forceinline__ void upsample(const void *lvl, int rw, int m0, int n_prev, const KerF &k,
-                                                    int li, int lg, floatx4 (&acc)[kRB]) {
+                                                    int li, int lg, floatx4 (&acc)[RB]) {
         static_assert(P2, "16-bit fragment reads need p = 2");
         (void)n_prev;
         const T *hi = static_cast<const T *>(lvl);
         const int e = m0 + 8 * min(lg, 2);
 #pragma unroll
-        for (int m = 0; m < kRB; ++m) {
+        for (int m = 0; m < RB; ++m) {
             const T *ph = hi + (rw + 16 * m + li) * SB + e;
             const T8 ah = *reinterpret_cast<const T8 *>(ph);
             const T8 al = *reinterpret_cast<const T8 *>(ph + kMixTM * SB);
@@ -296,14 +302,15 @@ struct Mix16 {
         for (int t = 0; t < 6; ++t) k.b[t] = ker_value(4 * t + lg, u.off, u.ph, nup, taps);
         return k;
     }
+    template <int RB>
     static __device__ __forceinline__ void upsample32(const void *lvl, int rw, int m0, int n_prev, const KerF32 &k,
-                                                      int li, int lg, floatx4 (&acc)[kRB]) {
+                                                      int li, int lg, floatx4 (&acc)[RB]) {
         const T *hi = static_cast<const T *>(lvl);
 #pragma unroll
         for (int t = 0; t < 6; ++t) {
             const int idx = min(m0 + 4 * t + lg, n_prev - 1);
 #pragma unroll
-            for (int m = 0; m < kRB; ++m) {
+            for (int m = 0; m < RB; ++m) {
                 const int o = (rw + 16 * m + li) * SB + idx;
                 acc[m] = mfma_16x16x4_f32((float)hi[o] + (float)hi[kMixTM * SB + o], k.b[t], acc[m]);
             }
@@ -330,10 +337,10 @@ struct IntC {
     static constexpr int value = V;
 };
 // The lower levels' windows are at most kMixS columns: at most kCBL column
-// blocks per wave, so their accumulators take 80 registers instead of 128
-// and a third pipeline stage fits (below).
-constexpr int kCBL = ((kMixS + 15) / 16 + kWC - 1) / kWC;
-static_assert(kCBL <= kCB, "lower-level accumulators");
+// blocks, which one wave of the lower levels' 4 x 1 layout holds for its two
+// row blocks in 80 accumulator registers (instead of 128), so that a third
+// pipeline stage fits (below).
+constexpr int kCBL = (kMixS + 15) / 16;
 // three lower-level stages (both planes, four K groups, the staged columns
 // rounded up to 64) fit the level buffer
 constexpr int kLowStageBytes = 2 * 4 * (((kMixS + 15) / 16 * 16 + 63) / 64) * 1024;
@@ -388,8 +395,14 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
     // window start); any other ratio takes element reads (hi + lo) into
     // FP32 products and the fragment of each block.  The FP32 form reads
     // elements at every ratio and shares the fragment for p <= 16.
-    auto upsample_level = [&](int j, int lo, int nb, auto &acc) {
+    // A wave layout: first row ry of the wave's RB 16-row blocks (RB from
+    // acc's type) and its column blocks cb = cb0 + cst i, i < NC.
+    //
+    // acc += H_up(level j + 1), read from the LDS level buffer (levels below
+    // the lowest)
+    auto upsample_level = [&](int j, int lo, int nb, auto &acc, int ry, int cb0, int cst) {
         constexpr int NC = sizeof(acc) / sizeof(acc[0]);
+        constexpr int RB = sizeof(acc[0]) / sizeof(floatx4);
         if (j < B.nlev - 1) {
             const int logp = B.shp[j + 1];
             const float *taps = tp + B.up_off[j + 1];
@@ -399,15 +412,15 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 const typename Op::KerF k0 = Op::ker(up_pos(lo, li, logp), nup, taps, lg);
 #pragma unroll
                 for (int i = 0; i < NC; ++i) {
-                    const int cb = wc + kWC * i;
+                    const int cb = cb0 + cst * i;
                     if (cb >= nb) continue;   // wave-uniform
                     const int i0 = lo + cb * 16;
                     const int m0 = (i0 >> logp) - nup - lo_prev;
                     if (logp <= 4) {
-                        Op::template upsample<false>(lvl, rw, m0, n_prev, k0, li, lg, acc[i]);
+                        Op::template upsample<false, RB>(lvl, ry, m0, n_prev, k0, li, lg, acc[i]);
                     } else {
                         const typename Op::KerF kb = Op::ker(up_pos(i0, li, logp), nup, taps, lg);
-                        Op::template upsample<false>(lvl, rw, m0, n_prev, kb, li, lg, acc[i]);
+                        Op::template upsample<false, RB>(lvl, ry, m0, n_prev, kb, li, lg, acc[i]);
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
@@ -415,10 +428,10 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 const typename Op::KerF k0 = Op::ker(up_pos(lo, li, 1), nup, taps, lg);
 #pragma unroll
                 for (int i = 0; i < NC; ++i) {
-                    const int cb = wc + kWC * i;
+                    const int cb = cb0 + cst * i;
                     if (cb >= nb) continue;   // wave-uniform
                     const int m0 = ((lo + cb * 16) >> 1) - nup - lo_prev;
-                    Op::template upsample<true>(lvl, rw, m0, n_prev, k0, li, lg, acc[i]);
+                    Op::template upsample<true, RB>(lvl, ry, m0, n_prev, k0, li, lg, acc[i]);
                     __builtin_amdgcn_sched_barrier(0);   // keep one block's LDS reads in flight at a time
                 }
             } else {
@@ -426,39 +439,40 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 // of its element reads instead of one per block); each block's
                 // tile goes to its accumulators, still zero at this point, so
                 // the sum is exact
-                const int ncb = min(NC, max(0, (nb - wc + kWC - 1) / kWC));
+                const int ncb = min(NC, max(0, (nb - cb0 + cst - 1) / cst));
 #pragma unroll 1
                 for (int i = 0; i < ncb; ++i) {
-                    const int i0 = lo + (wc + kWC * i) * 16;
+                    const int i0 = lo + (cb0 + cst * i) * 16;
                     const int m0 = (i0 >> logp) - nup - lo_prev;
                     const auto kb = Op::ker32(up_pos(i0, li, logp), nup, taps, lg);
-                    floatx4 t[kRB];
+                    floatx4 t[RB];
 #pragma unroll
-                    for (int m = 0; m < kRB; ++m) t[m] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    Op::upsample32(lvl, rw, m0, n_prev, kb, li, lg, t);
+                    for (int m = 0; m < RB; ++m) t[m] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Op::template upsample32<RB>(lvl, ry, m0, n_prev, kb, li, lg, t);
 #pragma unroll
                     for (int q = 0; q < NC; ++q)
                         if (q == i)   // wave-uniform
 #pragma unroll
-                            for (int m = 0; m < kRB; ++m) acc[q][m] += t[m];
+                            for (int m = 0; m < RB; ++m) acc[q][m] += t[m];
                 }
             }
         }
     };
 
     // level j >= 1: acc goes to the LDS level buffer for the next level up
-    auto write_level = [&](int n, int nb, const auto &acc) {
+    auto write_level = [&](int n, int nb, const auto &acc, int ry, int cb0, int cst) {
         constexpr int NC = sizeof(acc) / sizeof(acc[0]);
+        constexpr int RB = sizeof(acc[0]) / sizeof(floatx4);
 #pragma unroll
         for (int i = 0; i < NC; ++i) {
-            const int cb = wc + kWC * i;
+            const int cb = cb0 + cst * i;
             if (cb >= nb) continue;
             const int c = cb * 16 + li;
             if (c >= n) continue;
 #pragma unroll
-            for (int m = 0; m < kRB; ++m)
+            for (int m = 0; m < RB; ++m)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) Op::lvl_store(lvl, rw + 16 * m + 4 * lg + v, c, acc[i][m][v]);
+                for (int v = 0; v < 4; ++v) Op::lvl_store(lvl, ry + 16 * m + 4 * lg + v, c, acc[i][m][v]);
         }
     };
 
@@ -516,24 +530,33 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
         // that chunk's loads only) and one barrier, then the loads of chunk
         // c + DEPTH - 1 go out (into the stage and registers chunk c - 1 used)
         // before chunk c's MFMAs.  The top level runs two stages (a 256-column
-        // stage is 32 KB); the lower levels, whose windows stage at most 192
-        // columns (24 KB), run three, so that their short chunks overlap two
-        // chunks' load latency instead of one.
+        // stage is 32 KB) and the 2 x 2 wave layout (each W~ fragment feeds up
+        // to eight column blocks).  The lower levels, whose windows stage at
+        // most 192 columns (24 KB), run three stages, so that their short
+        // chunks overlap two chunks' load latency instead of one, and a 4 x 1
+        // layout: wave w owns rows 32 w .. 32 w + 31 (two row blocks) and every
+        // column block of the window, so each W~ fragment is loaded by one wave
+        // only (in the 2 x 2 layout the two waves of a row half load the same
+        // fragments, which at these few column blocks per chunk costs more
+        // than the second read of each y fragment from LDS).
         auto staged_level = [&](int j, auto ncb_c, auto depth_c, auto top_c) {
             constexpr int NC = decltype(ncb_c)::value;
             constexpr int DEPTH = decltype(depth_c)::value;
             constexpr bool TOP = decltype(top_c)::value;   // level 0
+            constexpr int RB = TOP ? kRB : kMixTM / 64;    // 16-row blocks per wave
+            const int ry = TOP ? rw : 32 * wave;           // first row of this wave
+            const int cb0 = TOP ? wc : 0, cst = TOP ? kWC : 1;
             const int lo = B.lo[j] + (it.t0 >> B.shP[j]);
             const int n = B.n[j];
             const int nb = (n + 15) >> 4;
-            floatx4 acc[NC][kRB];
+            floatx4 acc[NC][RB];
 #pragma unroll
             for (int i = 0; i < NC; ++i)
 #pragma unroll
-                for (int m = 0; m < kRB; ++m) acc[i][m] = floatx4{0.f, 0.f, 0.f, 0.f};
-            // this wave's column blocks cb = wc + kWC i, i < ncb
-            const int ncb = min(NC, max(0, (nb - wc + kWC - 1) / kWC));
-            upsample_level(j, lo, nb, acc);
+                for (int m = 0; m < RB; ++m) acc[i][m] = floatx4{0.f, 0.f, 0.f, 0.f};
+            // this wave's column blocks cb = cb0 + cst i, i < ncb
+            const int ncb = min(NC, max(0, (nb - cb0 + cst - 1) / cst));
+            upsample_level(j, lo, nb, acc, ry, cb0, cst);
             __syncthreads();   // every wave is done reading level j+1: the buffer now stages y
             {
                 const int sb = B.slice_begin[j], se = B.slice_begin[j + 1];
@@ -564,10 +587,10 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     c.vbase = (int)((g0 + (uint32_t)lane) * 16u);
                     c.vlast = (int)((g0 + (uint32_t)min((nq - 1) * 64 + lane, n - 1)) * 16u);
                     c.Lpad = ms.Lpad;
-                    Op::init_a(c.as, ms, it.r0 + rw, li, lg);
+                    Op::init_a(c.as, ms, it.r0 + ry, li, lg);
                 };
                 // per wave and chunk: nq copies per plane, then the W~ loads
-                auto issue = [&](const YCtx &c, int l0, int so, typename Op::FragA &fa) {
+                auto issue = [&](const YCtx &c, int l0, int so, typename Op::template FragA<RB> &fa) {
                     // the builtin's operands are plain locals: taken straight from
                     // the struct, the host pass drops the kernel's instantiation
                     const int soff = (l0 / Op::RING_G) * c.cap16;
@@ -592,10 +615,10 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 // in issue order, so the count allows exactly their loads
                 auto wait_chunk = [&](int ahead) {
                     if (ahead == 0) wait_vmcnt<0>();
-                    else if (nq == 1) wait_vmcnt<2 * 1 + Op::A_LOADS>();
-                    else if (nq == 2) wait_vmcnt<2 * 2 + Op::A_LOADS>();
-                    else if (nq == 3) wait_vmcnt<2 * 3 + Op::A_LOADS>();
-                    else wait_vmcnt<2 * 4 + Op::A_LOADS>();
+                    else if (nq == 1) wait_vmcnt<2 * 1 + Op::template a_loads<RB>>();
+                    else if (nq == 2) wait_vmcnt<2 * 2 + Op::template a_loads<RB>>();
+                    else if (nq == 3) wait_vmcnt<2 * 3 + Op::template a_loads<RB>>();
+                    else wait_vmcnt<2 * 4 + Op::template a_loads<RB>>();
                 };
                 if (sb < se) {
                     YCtx yc;   // the slice of the issue cursor
@@ -611,7 +634,7 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                             if (more) prepare(is, yc);
                         }
                     };
-                    typename Op::FragA fa[DEPTH];
+                    typename Op::template FragA<RB> fa[DEPTH];
 #pragma unroll
                     for (int p = 0; p < DEPTH - 1; ++p) {
                         if (more) {
@@ -639,7 +662,7 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                         for (int i = 0; i < NC; ++i) {
                             if (i >= ncb) break;   // wave-uniform
                             typename Op::FragB b;
-                            Op::read_b(b, st, ncs, wc + kWC * i, li, lg);
+                            Op::read_b(b, st, ncs, cb0 + cst * i, li, lg);
                             Op::mma(acc[i], fa[u], b);
                         }
                         ++c;
@@ -655,14 +678,14 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
             }
             __syncthreads();   // every wave is done reading the stages
             if constexpr (!TOP) {
-                write_level(n, nb, acc);
+                write_level(n, nb, acc, ry, cb0, cst);
                 __syncthreads();   // level j complete before it is read as prev
                 lo_prev = lo;
             } else {
                 epilogue(n, nb, acc);
             }
         };
-        for (int j = B.nlev - 1; j >= 1; --j) staged_level(j, IntC<kCBL>{}, IntC<3>{}, IntC<0>{});
+        for (int j = B.nlev - 1; j >= 1; --j) staged_level(j, IntC<kCBL>{}, IntC<3>{}, IntC<0>{});   // 4 x 1
         staged_level(0, IntC<kCB>{}, IntC<2>{}, IntC<1>{});
     } else {
         for (int j = B.nlev - 1; j >= 0; --j) {
@@ -703,10 +726,10 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     }
                 }
             }
-            upsample_level(j, lo, nb, acc);
+            upsample_level(j, lo, nb, acc, rw, wc, kWC);
             __syncthreads();   // every wave is done reading level j+1
             if (j > 0) {
-                write_level(n, nb, acc);
+                write_level(n, nb, acc, rw, wc, kWC);
                 __syncthreads();   // level j complete before it is read as prev
                 lo_prev = lo;
             } else {
