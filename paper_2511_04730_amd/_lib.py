@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblloid.so")
+# LLOID_LIB may name another build of the same sources (the host-sanitized
+# build the tests run the ABI checks against)
+LIB_PATH = os.environ.get("LLOID_LIB") or os.path.join(HERE, "liblloid.so")
 
 LLOID_OK = 0
 STATUS_NAMES = {0: "LLOID_OK", -1: "LLOID_E_ARG", -2: "LLOID_E_SHAPE", -3: "LLOID_E_LATENCY",
