@@ -332,8 +332,9 @@ def svd_measure(reps: int = 3, rows: int = 2048, n: int = 1024, rank: int = 40, 
     flops = iters * (4 * rows * n * rank + 2 * rank * rank * (rows + n) + 2 * rank ** 3 / 3) + 2 * rows * n * rank
     return {"ms": ms, "rows": rows, "taps": n, "rank": rank, "iterations": iters,
             "residual_over_optimum": resid / opt,
-            "roofline": {"bound": "alu", "achieved": flops / (ms / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
-                         "frac": flops / (ms / 1e3) / 1e12 / 78.6}}
+            "roofline": {"bound": "mfma", "achieved": flops / (ms / 1e3) / 1e12, "peak": 78.6, "unit": "TFLOP/s",
+                         "frac": flops / (ms / 1e3) / 1e12 / 78.6, "dtype": "f64",
+                         "limited_by": "latency of the per-step factorisation and launches"}}
 
 
 def grad_measure(reps: int = 3, refine_steps: int = 0):
