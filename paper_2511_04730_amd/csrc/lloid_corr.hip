@@ -11,8 +11,9 @@
 // so every basis fragment a wave reads from LDS feeds up to eight column
 // blocks (and every strain fragment up to kCorrMB row blocks); the wide
 // item spreads each stage's basis tile and barriers over many columns.  Taps advance in
-// stages: the basis tile and the strain segment of the next stage are
-// fetched into registers while the current stage's MFMAs run from LDS.
+// stages through two LDS buffers: while the current stage's MFMAs run from
+// one, the next stage (fetched into registers during the previous stage) is
+// stored into the other and the stage after it is fetched.
 //
 // Forms (the Op structs):
 //   F32   v_mfma_f32_16x16x4_f32, one tap per lane and K group;
@@ -381,7 +382,7 @@ __device__ __forceinline__ void ring_store4(void *ring, int64_t pos, int row, in
 template <typename Op>
 __global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict__ items, int32_t n_items,
                                                       int32_t group, const int64_t *__restrict__ stride_ctr) {
-    __shared__ __attribute__((aligned(16))) typename Op::Smem sm;
+    __shared__ __attribute__((aligned(16))) typename Op::Smem sm[2];
     const int item = xcd_item(group);
     if (item >= n_items) return;
     const CorrItem it = items[item];
@@ -400,14 +401,23 @@ __global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict
         for (int i = 0; i < CB; ++i) acc[m][i] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     const int64_t dbase = kstr * it.f + it.off + it.col0 + it.k0;
+    // Two LDS stage buffers: stage k is computed from buffer k mod 2 while
+    // stage k + 1 is stored into the other one and stage k + 2 is fetched
+    // into registers, one barrier per stage.
     typename Op::Regs g;
     Op::gload(g, it, posmod(dbase, it.cap), 0, tid);
+    Op::lstore(g, sm[0], it, tid);
+    if (Op::TK < it.klen) Op::gload(g, it, posmod(dbase + Op::TK, it.cap), Op::TK, tid);
+    int buf = 0;
     for (int kk = 0; kk < it.klen; kk += Op::TK) {
-        __syncthreads();   // the previous stage's LDS reads are done
-        Op::lstore(g, sm, it, tid);
-        __syncthreads();
-        if (kk + Op::TK < it.klen) Op::gload(g, it, posmod(dbase + kk + Op::TK, it.cap), kk + Op::TK, tid);
-        Op::compute(sm, acc, it.mb, ncb, wave, li, lg);
+        __syncthreads();   // stage kk is in sm[buf]; every wave is done reading sm[buf ^ 1]
+        if (kk + Op::TK < it.klen) {
+            Op::lstore(g, sm[buf ^ 1], it, tid);
+            if (kk + 2 * Op::TK < it.klen)
+                Op::gload(g, it, posmod(dbase + kk + 2 * Op::TK, it.cap), kk + 2 * Op::TK, tid);
+        }
+        Op::compute(sm[buf], acc, it.mb, ncb, wave, li, lg);
+        buf ^= 1;
     }
     const int64_t q0 = kstr * it.f + it.la + it.col0;
 #pragma unroll
