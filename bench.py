@@ -521,7 +521,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the filtering path has no multi-GPU "
+        print(json.dumps({"error": "the library runs on one GPU: the filtering path has no multi-GPU "
                                    "form; run with --gpus 1"}))
         return 2
     big = args.workload in ("batched", "largest")

@@ -49,7 +49,7 @@ typedef enum {
     LLOID_E_NOMEM = -4,       /* device or host allocation failed               */
     LLOID_E_HIP = -5,         /* a HIP runtime call failed                      */
     LLOID_E_STATE = -6,       /* call not valid in the plan's current state     */
-    LLOID_E_UNSUPPORTED = -7  /* valid request this build does not implement   */
+    LLOID_E_UNSUPPORTED = -7  /* valid request the library does not implement  */
 } lloid_status;
 
 /* Arithmetic of the correlation and mixing contractions (accumulation is

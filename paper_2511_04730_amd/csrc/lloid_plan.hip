@@ -1,4 +1,4 @@
-// Host side of the LLOID C ABI: plan construction, work tables, stride driver.
+// Host side of the LLOID C ABI: plan construction, work tables, stride launches.
 //
 // Plan construction validates every bank, groups each bank's slices by rate
 // into a chain of levels (top rate first; Sec. II.C.1 slices, Sec. II.C.3
@@ -375,7 +375,7 @@ const char *lloid_status_string(lloid_status s) {
         case LLOID_E_NOMEM: return "out of device or host memory";
         case LLOID_E_HIP: return "HIP runtime error";
         case LLOID_E_STATE: return "invalid plan state for this call";
-        case LLOID_E_UNSUPPORTED: return "unsupported by this build";
+        case LLOID_E_UNSUPPORTED: return "valid request the library does not implement";
     }
     return "unknown status";
 }
