@@ -177,9 +177,10 @@ hipError_t launch_sum_f64(hipStream_t, const double *part, int32_t n, double *ou
 hipError_t launch_upsample_adjoint(hipStream_t, const float *g, int64_t g_ld, int64_t g_lo, int64_t ng,
                                    float *out, int64_t o_ld, int64_t a_lo, int64_t na, int32_t rows,
                                    int32_t p, int32_t nup, const float *taps);
-hipError_t launch_gemm_f32(hipStream_t, const float *A, int64_t sam, int64_t sak, const float *B,
-                           int64_t sbk, int64_t sbn, int64_t M, int64_t N, int64_t K, int64_t ksplit,
-                           float *part);
+hipError_t launch_gemm_abt(hipStream_t, const float *A, int64_t lda, const float *B, int64_t ldb, int32_t M,
+                           int32_t N, int64_t K, int64_t ksplit, float *part);
+hipError_t launch_gemm_atb(hipStream_t, const float *W, int32_t ldw, const float *G, int64_t ldg, int32_t K,
+                           int64_t n_out, float alpha, float *out, int64_t ldo);
 hipError_t launch_sum_parts(hipStream_t, const float *part, int32_t nsplit, int64_t plane, int32_t rows,
                             int32_t cols, int64_t p_ld, float *dst, int64_t d_ld, float alpha,
                             int32_t accumulate);

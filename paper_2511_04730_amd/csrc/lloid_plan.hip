@@ -1076,12 +1076,15 @@ lloid_status lloid_inspect(lloid_plan *P, int32_t what, int32_t index, int32_t d
 // three contractions of dL/dW, dL/dY and dL/dU (the last one on the
 // correlation kernel: a Hankel window of the decimated strain again).
 namespace {
-constexpr int64_t kGradSplitW = 16384;   // K split of dW = 2 G Y^T (K = time)
 constexpr int64_t kGradSplitU = 8192;    // K split of dU (K = time)
 // zero tail of the gradient's linear strain segments: the correlation reads
 // up to kCorrTQ + 64 samples past a window start
 constexpr int64_t kSegPad = kCorrTQ + 64;
-constexpr int kLossBlocks = 64;
+constexpr int kLossBlocks = 1024;   // residual work groups (loss partials) per stride, bank and detector
+
+// K split of dW = 2 G Y^T (K = time at the slice's rate): 128 splits of
+// the top rate's 64 s segment, at least 512 samples each
+int64_t dw_split(int64_t k) { return std::max<int64_t>(512, round_up((k + 127) / 128, 256)); }
 
 int64_t seg_lo(const PBank &b, int j, int nup) {
     int64_t lo = 0;
@@ -1147,9 +1150,11 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
     ST_OK(get(&loss_d, 1, true));
     int64_t *zero = nullptr;
     ST_OK(get(&zero, 1, true));
+    // residual rows [2 M][RLD], zero past TF (the products read whole 32-sample chunks)
+    const int64_t RLD = round_up(TF, 64);
     std::vector<float *> R(nbd, nullptr);
     for (size_t b = 0; b < P->banks.size(); ++b)
-        for (int d = 0; d < ND; ++d) ST_OK(get(&R[b * ND + d], (size_t)2 * P->banks[b].M * TF, false));
+        for (int d = 0; d < ND; ++d) ST_OK(get(&R[b * ND + d], (size_t)2 * P->banks[b].M * RLD, true));
     const int ns = (int)P->slices.size();
     std::vector<float *> yseg(ns, nullptr);
     std::vector<int64_t> qld(ns), slo(ns), sq(ns);
@@ -1180,7 +1185,7 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
             for (int d = 0; d < ND; ++d) {
                 const int64_t so = pb.series_off + (int64_t)d * pb.M * F * 2;
                 HIP_OK(launch_residual(st, series + so, target + (int64_t)k * P->series_floats + so, pb.M, F,
-                                       R[b * ND + d], TF, (int64_t)k * F,
+                                       R[b * ND + d], RLD, (int64_t)k * F,
                                        loss_part + ((int64_t)k * nbd + b * ND + d) * kLossBlocks, kLossBlocks));
             }
         }
@@ -1210,14 +1215,13 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
     for (int i = 0; i < ns; ++i) {
         const PSlice &s = P->slices[i];
         const int64_t rows = 2LL * P->banks[s.bank].M;
-        pmax = std::max(pmax, ((sq[i] + kGradSplitW - 1) / kGradSplitW) * rows * s.L);
+        pmax = std::max(pmax, ((sq[i] + dw_split(sq[i]) - 1) / dw_split(sq[i])) * rows * s.L);
         pmax = std::max(pmax, (qld[i] / kGradSplitU + 1) * s.Lpad * s.N);
-        pmax = std::max(pmax, (int64_t)s.L * sq[i]);
         dymax = std::max(dymax, (int64_t)s.Lpad * qld[i]);
     }
     for (auto &pb : P->banks)
         for (int j = 1; j < pb.nlev; ++j)
-            gmax = std::max<int64_t>(gmax, 2LL * pb.M * (seg_hi(pb, j, nup, TF) - seg_lo(pb, j, nup)));
+            gmax = std::max<int64_t>(gmax, 2LL * pb.M * round_up(seg_hi(pb, j, nup, TF) - seg_lo(pb, j, nup), 64));
     float *part = nullptr, *dy = nullptr, *g1 = nullptr, *g2 = nullptr;
     ST_OK(get(&part, (size_t)pmax, false));
     ST_OK(get(&dy, (size_t)dymax, false));
@@ -1243,33 +1247,32 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
         const int64_t rows = 2LL * pb.M;
         for (int d = 0; d < ND; ++d) {
             const float *G = R[b * ND + d];
-            int64_t glo = 0, gn = TF;
+            int64_t glo = 0, gn = TF, gld = RLD;   // G: [rows][gld], level indices glo .. glo + gn - 1
             float *bufs[2] = {g1, g2};
             for (int j = 0; j < pb.nlev; ++j) {
                 if (j > 0) {
                     const int p = pb.rates[j - 1] / pb.rates[j];
                     const int64_t lo = seg_lo(pb, j, nup), n = seg_hi(pb, j, nup, TF) - lo;
                     float *out = bufs[j & 1];
-                    HIP_OK(launch_upsample_adjoint(st, G, gn, glo, gn, out, n, lo, n, (int32_t)rows, p, nup,
+                    const int64_t nld = round_up(n, 64);
+                    HIP_OK(launch_upsample_adjoint(st, G, gld, glo, gn, out, nld, lo, n, (int32_t)rows, p, nup,
                                                    P->d_uptaps + (p - 1) * kUpTaps));
                     G = out;
                     glo = lo;
                     gn = n;
+                    gld = nld;
                 }
                 for (int i : pb.slices) {
                     const PSlice &s = P->slices[i];
                     if (s.level != j) continue;
                     const float *Y = yseg[i] + (int64_t)d * s.Lpad * qld[i];
-                    // dW = 2 G Y^T
-                    const int64_t nw = (gn + kGradSplitW - 1) / kGradSplitW;
-                    HIP_OK(launch_gemm_f32(st, G, gn, 1, Y, 1, qld[i], rows, s.L, gn, kGradSplitW, part));
+                    // dW = 2 G Y^T  (Y rows zero past L and columns zero past gn, like G's)
+                    const int64_t ks = dw_split(gn), nw = (gn + ks - 1) / ks;
+                    HIP_OK(launch_gemm_abt(st, G, gld, Y, qld[i], (int32_t)rows, s.L, gn, ks, part));
                     HIP_OK(launch_sum_parts(st, part, (int32_t)nw, rows * s.L, (int32_t)rows, s.L, s.L,
                                             dW + offW[i], s.L, 2.0f, d > 0));
-                    // dY = 2 W^T G  into [Lpad][qld], zero padded
-                    HIP_OK(hipMemsetAsync(dy, 0, sizeof(float) * s.Lpad * qld[i], st));
-                    HIP_OK(launch_gemm_f32(st, s.W32, 1, s.Lpad, G, gn, 1, s.L, gn, rows, rows, part));
-                    HIP_OK(launch_sum_parts(st, part, 1, (int64_t)s.L * gn, s.L, (int32_t)gn, gn, dy, qld[i],
-                                            2.0f, 0));
+                    // dY = 2 W^T G  into [Lpad][qld] (qld == gld), every element written
+                    HIP_OK(launch_gemm_atb(st, s.W32, s.Lpad, G, gld, (int32_t)rows, qld[i], 2.0f, dy, qld[i]));
                     // dU[l][n] = sum_q dY[l][q] d[q + lo - delay - (N-1) + n]
                     std::vector<CorrItem> items;
                     const int64_t nsu = (qld[i] + kGradSplitU - 1) / kGradSplitU;

@@ -50,17 +50,18 @@ def _gpu_series(plan, x, T):
     return np.stack(out)
 
 
-@pytest.mark.parametrize("slices", [SL, [(1024, 0.0, 300, 12), (256, 0.75, 300, 8)]])
-def test_backward_matches_oracle_for_a_given_residual(lib, slices):
+@pytest.mark.parametrize("slices,n_up", [(SL, 8), ([(1024, 0.0, 300, 12), (256, 0.75, 300, 8)], 8), (SL, 4)])
+def test_backward_matches_oracle_for_a_given_residual(lib, slices, n_up):
     """The backward arithmetic alone: the target is the plan's own forward
     output minus a known residual E (the oracle gets its own output minus
     the same E), so both differentiate the same R = E; 2-rate (x2 stages)
-    and x4-stage banks."""
+    and x4-stage banks, and a shorter interpolator (N_up = 4, the transposed
+    stage's general kernel)."""
     bank = synth.chirp_bank(F, 10, 25.0, (1.2, 1.5), slices, seed=[13, 1, 0], keep_templates=True)
     T = 4
     x = synth.gaussian_strain(13, 1, T * F)
-    cfg = O.OracleConfig(F, normalize=False)
-    plan = lib.LloidPlan([bank], F, 1, "fp32", normalize=False)
+    cfg = O.OracleConfig(F, n_up=n_up, normalize=False)
+    plan = lib.LloidPlan([bank], F, 1, "fp32", normalize=False, n_up=n_up)
     E = np.random.default_rng(3).standard_normal((2 * bank.n_templates, T * F)) * 0.1
     tg = _gpu_series(plan, x, T) - _target_layout(E, bank.n_templates, T).astype(np.float64)
     loss, dW, dU = plan.grad(torch.from_numpy(x.astype(np.float32)).cuda(),

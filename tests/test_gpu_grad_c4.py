@@ -6,7 +6,7 @@ realistic bank (1024 templates, 5 rates 4096..256 Hz, slices of 1024 to
    20 s (the 16-64 s slice sees strain in the last 4 s), with a known
    residual E (target = the plan's own output - E, the oracle's target its
    own output - E): every slice's dW and dU, including the split-K paths
-   (20 x 4096 time samples: five dW splits and ten dU splits at the top
+   (20 x 4096 time samples: 107 dW splits and ten dU splits at the top
    rate).
 2. 100 refinement steps on the whole bank over 64 s with FP64 CholeskyQR2
    on the GPU after each: loss non-increasing, orthonormal bases to 1e-12,
