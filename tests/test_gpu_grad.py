@@ -78,6 +78,36 @@ def test_backward_matches_oracle_for_a_given_residual(lib, slices, n_up):
     assert plan.stride == T
 
 
+def test_backward_at_another_top_rate(lib):
+    """The backward at a 768 Hz top rate and 13 templates (26 rows, not a
+    multiple of the products' 32-row blocks; every lower rate's segment a
+    length that is not a multiple of the 64-sample row padding), against the
+    oracle for a known residual as above."""
+    Fr, T, M = 768, 4, 13
+    sl = [(768, 0.0, 300, 12), (384, 0.25, 260, 10), (192, 0.75, 300, 8)]
+    bank = synth.chirp_bank(Fr, M, 25.0, (1.2, 1.5), sl, seed=[13, 2, 0], keep_templates=True)
+    x = synth.gaussian_strain(17, 1, T * Fr)
+    cfg = O.OracleConfig(Fr, normalize=False)
+    plan = lib.LloidPlan([bank], Fr, 1, "fp32", normalize=False)
+    xs = torch.from_numpy(x.astype(np.float32)).cuda()
+    own = np.stack([plan.push(xs[:, k * Fr:(k + 1) * Fr].contiguous())[0].double().cpu().numpy()
+                    for k in range(T)])
+    E = np.random.default_rng(5).standard_normal((2 * M, T * Fr)) * 0.1
+    z = E[0::2] + 1j * E[1::2]
+    lay = np.stack([z.real, z.imag], axis=-1).reshape(M, T, Fr, 2).transpose(1, 0, 2, 3).reshape(T, M * Fr * 2)
+    tg = torch.from_numpy((own - lay).astype(np.float32)).cuda()
+    loss, dW, dU = plan.grad(xs, tg)
+    rho = O.snr_series(x[0], bank, cfg, 0, T * Fr, mixing=[s.mixing for s in bank.slices])
+    L_ref, dW_ref, dU_ref = O.loss_and_grad(x[0], bank, rho - E, cfg, 0, T * Fr)
+    print(f"loss gpu {loss:.6e} oracle {L_ref:.6e}")
+    assert abs(loss - L_ref) <= 1e-5 * L_ref
+    for s in range(len(bank.slices)):
+        ew = np.abs(dW[s].cpu().numpy() - dW_ref[s]).max() / np.abs(dW_ref[s]).max()
+        eu = np.abs(dU[s].cpu().numpy() - dU_ref[s]).max() / np.abs(dU_ref[s]).max()
+        print(f"slice {s}: dW rel err {ew:.2e}, dU rel err {eu:.2e}")
+        assert ew < 1e-4 and eu < 1e-4
+
+
 def test_gradient_matches_oracle(lib, problem):
     """Realistic target (the uncompressed bank's output): near the SVD
     optimum the gradient is a small residual, so the FP32 forward error
