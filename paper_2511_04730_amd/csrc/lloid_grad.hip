@@ -11,30 +11,35 @@
 // (phase 0: weight 1 at q = m, the copy case of Eq. (upsample)).
 #include <hip/hip_runtime.h>
 
+#include "lloid_device.h"
 #include "lloid_internal.h"
 #include "lloid_mfma.h"
 
 namespace lloid {
 
 // ---------------------------------------------------------------- capture
-// dst[r * dst_ld + dst_off + c] = ring[r * ring_ld + ((a + c) mod cap)], c < len
-__global__ void copy_window_kernel(const float *__restrict__ ring, int64_t ring_ld, int32_t cap, int64_t a,
-                                   int32_t len, int32_t rows, float *__restrict__ dst, int64_t dst_ld,
-                                   int64_t dst_off) {
-    const int r = blockIdx.y;
-    if (r >= rows) return;
-    int64_t p = a % cap;
-    if (p < 0) p += cap;
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < len; c += gridDim.x * blockDim.x)
-        dst[r * dst_ld + dst_off + c] = ring[r * ring_ld + p + c];   // mirror ring: p + c < 2 cap
+// One stride's capture, every ring in one launch: work group (x, g) copies
+// row g - row0 of item row_item[g], positions a .. a + len - 1 with
+// a = base + k step, from its mirror ring (a basis-output ring in 4-output
+// groups, or a plain stream ring) to dst row r at column a - dst_lo.
+__global__ __launch_bounds__(256) void capture_kernel(const CaptureItem *__restrict__ items,
+                                                      const int32_t *__restrict__ row_item, int64_t k) {
+    const CaptureItem it = items[row_item[blockIdx.y]];
+    const int r = (int)blockIdx.y - it.row0;
+    const int64_t a = it.base + k * it.step;
+    const int64_t p0 = posmod(a, it.cap);
+    float *d = it.dst + r * it.dst_ld + (a - it.dst_lo);
+    for (int c = blockIdx.x * 256 + threadIdx.x; c < it.len; c += gridDim.x * 256) {
+        const int64_t p = p0 + c;   // mirror ring: p < 2 cap
+        d[c] = it.grouped ? it.src[ring_index<4>(p, r, it.cap)] : it.src[r * it.src_ld + p];
+    }
 }
 
-hipError_t launch_copy_window(hipStream_t st, const float *ring, int64_t ring_ld, int32_t cap, int64_t a,
-                              int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off) {
-    if (len <= 0 || rows <= 0) return hipSuccess;
-    dim3 grid((unsigned)std::min<int64_t>((len + 255) / 256, 64), rows);
-    hipLaunchKernelGGL(copy_window_kernel, grid, dim3(256), 0, st, ring, ring_ld, cap, a, len, rows, dst, dst_ld,
-                       dst_off);
+hipError_t launch_capture(hipStream_t st, const CaptureItem *items, const int32_t *row_item, int32_t rows,
+                          int32_t max_len, int64_t k) {
+    if (rows <= 0 || max_len <= 0) return hipSuccess;
+    dim3 grid((unsigned)std::min(16, (max_len + 255) / 256), (unsigned)rows);
+    hipLaunchKernelGGL(capture_kernel, grid, dim3(256), 0, st, items, row_item, k);
     return hipGetLastError();
 }
 

@@ -169,8 +169,18 @@ hipError_t launch_ring_gather(hipStream_t, int precision, const void *ring, int3
                               int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off);
 
 // gradient and re-orthonormalisation (lloid_grad.hip)
-hipError_t launch_copy_window(hipStream_t, const float *ring, int64_t ring_ld, int32_t cap, int64_t a,
-                              int32_t len, int32_t rows, float *dst, int64_t dst_ld, int64_t dst_off);
+// the gradient's capture of one stride: item rows are copied from their
+// mirror rings (basis outputs in 4-output groups, or plain streams)
+struct CaptureItem {
+    const float *src;
+    int64_t src_ld;   // plain ring: floats per row
+    int64_t base, step;
+    float *dst;
+    int64_t dst_ld, dst_lo;
+    int32_t cap, grouped, len, row0;
+};
+hipError_t launch_capture(hipStream_t, const CaptureItem *items, const int32_t *row_item, int32_t rows,
+                          int32_t max_len, int64_t k);
 hipError_t launch_residual(hipStream_t, const float *series, const float *target, int32_t M, int32_t F,
                            float *R, int64_t ld, int64_t t0, double *loss_part, int32_t blocks);
 hipError_t launch_sum_f64(hipStream_t, const double *part, int32_t n, double *out);

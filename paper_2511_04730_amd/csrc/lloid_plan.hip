@@ -1177,6 +1177,42 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
         ST_OK(get(&dseg[D], (size_t)ND * (dlen[D] + kSegPad), true));
     }
 
+    // ---- capture table: per stride, every slice's basis outputs (its L rows,
+    // `rate` new positions at k rate + la) and every decimated stream (F / D
+    // new samples) into the linear segments, one launch
+    std::vector<CaptureItem> cap;
+    std::vector<int32_t> caprow;
+    int32_t cap_len = 0;
+    auto add_item = [&](CaptureItem it, int rows) {
+        it.row0 = (int32_t)caprow.size();
+        for (int r = 0; r < rows; ++r) caprow.push_back((int32_t)cap.size());
+        cap_len = std::max(cap_len, it.len);
+        cap.push_back(it);
+    };
+    for (int i = 0; i < ns; ++i) {
+        const PSlice &s = P->slices[i];
+        for (int d = 0; d < ND; ++d)
+            add_item(CaptureItem{s.yring + d * s.ydet, 0, s.la, s.rate, yseg[i] + (int64_t)d * s.Lpad * qld[i], qld[i],
+                                 slo[i], s.capY, 1, s.rate, 0},
+                     s.L);
+    }
+    for (auto &kv : dseg) {
+        const int D = kv.first;
+        const Ring &r = P->rings[D];
+        const int f = F / D;
+        for (int d = 0; d < ND; ++d)
+            add_item(CaptureItem{r.base + d * r.det_stride, 0, D == 1 ? 0 : -(int64_t)P->ndown, D == 1 ? F : f,
+                                 kv.second + d * (dlen[D] + kSegPad), 0, dlo[D], r.cap, 0, f, 0},
+                     1);
+    }
+    const int32_t cap_rows = (int32_t)caprow.size();
+    CaptureItem *d_cap = nullptr;
+    int32_t *d_caprow = nullptr;
+    ST_OK(get(&d_cap, cap.size(), false));
+    ST_OK(get(&d_caprow, std::max<size_t>(caprow.size(), 1), false));
+    HIP_OK(hipMemcpyAsync(d_cap, cap.data(), sizeof(CaptureItem) * cap.size(), hipMemcpyHostToDevice, st));
+    HIP_OK(hipMemcpyAsync(d_caprow, caprow.data(), sizeof(int32_t) * caprow.size(), hipMemcpyHostToDevice, st));
+
     // ---- forward with capture
     for (int k = 0; k < T; ++k) {
         ST_OK(enqueue_stride(P, st, strain + (int64_t)k * F, 0, series, peaks, TF));
@@ -1189,22 +1225,7 @@ lloid_status lloid_grad(lloid_plan *P, const float *strain, int32_t T, const flo
                                        loss_part + ((int64_t)k * nbd + b * ND + d) * kLossBlocks, kLossBlocks));
             }
         }
-        for (int i = 0; i < ns; ++i) {
-            const PSlice &s = P->slices[i];
-            const int64_t a = (int64_t)k * s.rate + s.la;
-            for (int d = 0; d < ND; ++d)
-                HIP_OK(launch_ring_gather(st, LLOID_FP32, s.yring + d * s.ydet, s.Lpad, s.capY, a, s.rate, s.L,
-                                          yseg[i] + (int64_t)d * s.Lpad * qld[i], qld[i], a - slo[i]));
-        }
-        for (auto &kv : dseg) {
-            const int D = kv.first;
-            const Ring &r = P->rings[D];
-            const int f = F / D;
-            const int64_t a = D == 1 ? (int64_t)k * F : (int64_t)k * f - P->ndown;
-            for (int d = 0; d < ND; ++d)
-                HIP_OK(launch_copy_window(st, r.base + d * r.det_stride, 0, r.cap, a, f, 1,
-                                          kv.second + d * (dlen[D] + kSegPad), 0, a - dlo[D]));
-        }
+        HIP_OK(launch_capture(st, d_cap, d_caprow, cap_rows, cap_len, k));
     }
     P->stride = T;
     P->use_graph = graph;
