@@ -345,6 +345,8 @@ constexpr int kCBL = (kMixS + 15) / 16;
 // rounded up to 64) fit the level buffer
 constexpr int kLowStageBytes = 2 * 4 * (((kMixS + 15) / 16 * 16 + 63) / 64) * 1024;
 static_assert(3 * kLowStageBytes <= Mix16<__bf16, bf16x8, true>::LVL_BYTES, "three lower-level stages");
+// two private stages per wave (both planes, four K groups, 64 columns)
+static_assert(4 * 2 * 2 * 4 * 1024 <= Mix16<__bf16, bf16x8, true>::LVL_BYTES, "private lower-level stages");
 
 // s_waitcnt vmcnt(N) (gfx9 encoding: low four bits and bits 15:14; the LDS
 // and export counters left at their maxima)
@@ -538,11 +540,21 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
         // column block of the window, so each W~ fragment is loaded by one wave
         // only (in the 2 x 2 layout the two waves of a row half load the same
         // fragments, which at these few column blocks per chunk costs more
-        // than the second read of each y fragment from LDS).
-        auto staged_level = [&](int j, auto ncb_c, auto depth_c, auto top_c) {
+        // than the second read of each y fragment from LDS).  A lower level
+        // whose window fits one 64-column copy (the rates an eighth of the
+        // top rate and below) gives every wave two stages of its own, into
+        // which it copies all four K groups itself: its chunks then wait for
+        // their own loads only, with no barrier (four times the copies of
+        // the small window, from the L2).
+        auto staged_level = [&](int j, auto ncb_c, auto depth_c, auto top_c, auto priv_c) {
             constexpr int NC = decltype(ncb_c)::value;
             constexpr int DEPTH = decltype(depth_c)::value;
             constexpr bool TOP = decltype(top_c)::value;   // level 0
+            // windows of at most 64 columns: every wave copies all four K
+            // groups into DEPTH stages of its own, so a chunk needs its own
+            // loads only (a wait, no barrier)
+            constexpr bool PRIV = decltype(priv_c)::value;
+            static_assert(!PRIV || (NC * 16 <= 64 && !TOP), "private stages: one 64-column copy");
             constexpr int RB = TOP ? kRB : kMixTM / 64;    // 16-row blocks per wave
             const int ry = TOP ? rw : 32 * wave;           // first row of this wave
             const int cb0 = TOP ? wc : 0, cst = TOP ? kWC : 1;
@@ -563,6 +575,7 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 const int ncs = min(kMixTN, (nb * 16 + 63) & ~63);   // staged columns
                 const int nq = ncs >> 6;                             // 64-column copies per plane and group
                 const int stage_bytes = Op::PLANES * 4 * nq * 1024;  // DEPTH stages fit LVL_BYTES
+                const int wbase = PRIV ? wave * DEPTH * stage_bytes : 0;   // this wave's stages (PRIV)
                 const uint32_t rate = (uint32_t)B.rate[j];
                 // Per slice (set up once when the issue cursor reaches it): the
                 // ring's buffer resource and, per lane, the byte offset of each
@@ -595,10 +608,24 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                     // the struct, the host pass drops the kernel's instantiation
                     const int soff = (l0 / Op::RING_G) * c.cap16;
                     __amdgpu_buffer_rsrc_t ry = c.ry;
-                    const int vb = c.vbase, vl = c.vlast, pln = c.plane;
+                    const int vb = c.vbase, vl = c.vlast, pln = c.plane, c16 = c.cap16;
+                    typedef __attribute__((address_space(3))) void *lds_ptr;
+                    if constexpr (PRIV) {
+                        // one copy (nq = 1) per plane and K group g, from the
+                        // group's ring rows (g cap16 bytes past group 0)
+                        const int vl0 = vl - wave * c16;
+#pragma unroll
+                        for (int pl = 0; pl < Op::PLANES; ++pl)
+#pragma unroll
+                            for (int g = 0; g < 4; ++g)
+                                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                                    ry, (lds_ptr)(lds + wbase + so + (pl * 4 + g) * ncs * 16), 16, vl0,
+                                    soff + pl * pln + g * c16, 0, 0);
+                        Op::load_a(fa, c.as, l0);
+                        return;
+                    }
 #pragma unroll
                     for (int pl = 0; pl < Op::PLANES; ++pl) {
-                        typedef __attribute__((address_space(3))) void *lds_ptr;
                         char *dst = lds + so + (pl * 4 + wave) * ncs * 16;
                         const int sp = soff + pl * pln;
                         // copies 0 .. nq - 2 (wave-uniform count), then the last.  The
@@ -615,6 +642,7 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 // in issue order, so the count allows exactly their loads
                 auto wait_chunk = [&](int ahead) {
                     if (ahead == 0) wait_vmcnt<0>();
+                    else if (PRIV) wait_vmcnt<2 * 4 + Op::template a_loads<RB>>();
                     else if (nq == 1) wait_vmcnt<2 * 1 + Op::template a_loads<RB>>();
                     else if (nq == 2) wait_vmcnt<2 * 2 + Op::template a_loads<RB>>();
                     else if (nq == 3) wait_vmcnt<2 * 3 + Op::template a_loads<RB>>();
@@ -650,14 +678,14 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                         constexpr int u = decltype(u_c)::value;
                         if (c >= issued) return false;
                         wait_chunk(issued - c - 1);
-                        __syncthreads();   // ... for every wave; stage (c - 1) mod DEPTH is free
+                        if constexpr (!PRIV) __syncthreads();   // ... for every wave; stage (c - 1) mod DEPTH is free
                         if (more) {
                             constexpr int q = (u + DEPTH - 1) % DEPTH;
                             issue(yc, il, q * stage_bytes, fa[q]);
                             ++issued;
                             advance();
                         }
-                        const char *st = lds + u * stage_bytes;
+                        const char *st = lds + wbase + u * stage_bytes;
 #pragma unroll
                         for (int i = 0; i < NC; ++i) {
                             if (i >= ncb) break;   // wave-uniform
@@ -685,8 +713,13 @@ __global__ __launch_bounds__(256, 2) void mix_kernel(const MixItem *__restrict__
                 epilogue(n, nb, acc);
             }
         };
-        for (int j = B.nlev - 1; j >= 1; --j) staged_level(j, IntC<kCBL>{}, IntC<3>{}, IntC<0>{});   // 4 x 1
-        staged_level(0, IntC<kCB>{}, IntC<2>{}, IntC<1>{});
+        for (int j = B.nlev - 1; j >= 1; --j) {   // 4 x 1
+            if (B.n[j] <= 64)
+                staged_level(j, IntC<4>{}, IntC<2>{}, IntC<0>{}, IntC<1>{});
+            else
+                staged_level(j, IntC<kCBL>{}, IntC<3>{}, IntC<0>{}, IntC<0>{});
+        }
+        staged_level(0, IntC<kCB>{}, IntC<2>{}, IntC<1>{}, IntC<0>{});
     } else {
         for (int j = B.nlev - 1; j >= 0; --j) {
             const int lo = B.lo[j] + (it.t0 >> B.shP[j]);
