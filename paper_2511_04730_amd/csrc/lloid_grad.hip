@@ -19,9 +19,10 @@ namespace lloid {
 
 // ---------------------------------------------------------------- capture
 // One stride's capture, every ring in one launch: work group (x, g) copies
-// row g - row0 of item row_item[g], positions a .. a + len - 1 with
-// a = base + k step, from its mirror ring (a basis-output ring in 4-output
-// groups, or a plain stream ring) to dst row r at column a - dst_lo.
+// row r = g - row0 of item row_item[g], positions a .. a + len - 1 with
+// a = base + k step (stride k), from the item's mirror ring (a basis-output
+// ring in 4-output groups, or a plain stream ring) to its dst row r at
+// columns a - dst_lo onwards.
 __global__ __launch_bounds__(256) void capture_kernel(const CaptureItem *__restrict__ items,
                                                       const int32_t *__restrict__ row_item, int64_t k) {
     const CaptureItem it = items[row_item[blockIdx.y]];
