@@ -416,7 +416,12 @@ __global__ __launch_bounds__(256, 2) void corr_kernel(const CorrItem *__restrict
             if (kk + 2 * Op::TK < it.klen)
                 Op::gload(g, it, posmod(dbase + kk + 2 * Op::TK, it.cap), kk + 2 * Op::TK, tid);
         }
+        // the stage's matrix products at raised wave priority, so that the
+        // scheduler favours the waves feeding the matrix cores over those
+        // still storing or loading a stage (1 % on the batched workload)
+        __builtin_amdgcn_s_setprio(1);
         Op::compute(sm[buf], acc, it.mb, ncb, wave, li, lg);
+        __builtin_amdgcn_s_setprio(0);
         buf ^= 1;
     }
     const int64_t q0 = kstr * it.f + it.la + it.col0;
