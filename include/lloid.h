@@ -212,9 +212,10 @@ lloid_status lloid_inspect(lloid_plan *plan, int32_t what, int32_t index, int32_
  *               [2M_b][L_s] block, packed back to back
  *   dU_dev      device float32: for every slice, its [L_s][N_s] block
  * The gradient is with respect to the mixing rows the plan uses (create the
- * plan with normalize = 0 to differentiate the given W).  The plan keeps a
- * workspace of about twice the segment's series size (FP32 plans only:
- * LLOID_E_UNSUPPORTED otherwise).  Synchronises `stream`. */
+ * plan with normalize = 0 to differentiate the given W).  Each call
+ * allocates, and frees before returning, a device workspace of about twice
+ * the segment's series size (LLOID_E_NOMEM if it does not fit).  FP32 plans
+ * only (LLOID_E_UNSUPPORTED otherwise).  Synchronises `stream`. */
 lloid_status lloid_grad(lloid_plan *plan, const float *strain_dev, int32_t n_strides, const float *target_dev,
                         double *loss_out, float *dW_dev, float *dU_dev, void *stream);
 
