@@ -337,14 +337,16 @@ def svd_measure(reps: int = 3, rows: int = 2048, n: int = 1024, rank: int = 40, 
                          "limited_by": "latency of the per-step factorisation and launches"}}
 
 
-def grad_measure(reps: int = 3, refine_steps: int = 0):
+def grad_measure(reps: int = 3, refine_steps: int = 0, tune: bool = False):
     """The gradient workload: the realistic bank (1024 templates, 5 rates)
     at half its basis counts (L = 20/30/40/50/60), 64 s of strain at
     4096 Hz, target = the FP32 output of the same bank at its full basis
     counts.  Times lloid_grad (forward over the 64 strides with capture,
     residual, transposed chain and the dW / dU contractions, synchronised)
     as the mean of `reps` calls after one untimed, and optionally
-    `refine_steps` steps of refinement with FP64 re-orthonormalisation."""
+    `refine_steps` steps of refinement with FP64 re-orthonormalisation.
+    With `tune`, the FP32 plan's tiling is autotuned on the segment's first
+    four strides first (the forward strides inside the gradient use it)."""
     import numpy as np
     import torch
     import synth
@@ -360,6 +362,11 @@ def grad_measure(reps: int = 3, refine_steps: int = 0):
     torch.cuda.synchronize()
     tp.close()
     plan = LloidPlan([half], F, 1, "fp32", normalize=False)
+    keys = ("corr_cols", "corr_split", "corr_group", "mix_group", "mix_tblock")
+    if tune:
+        from paper_2511_04730_amd.autotune import autotune
+        autotune(plan, [x[:, k * F:(k + 1) * F].contiguous() for k in range(4)])
+    tiling = {k: plan.option(k) for k in keys}
     loss, _, _ = plan.grad(x, tg)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -375,7 +382,7 @@ def grad_measure(reps: int = 3, refine_steps: int = 0):
         fwd += T * (2.0 * s.n_basis * s.n_taps * s.rate + 2.0 * 2 * M * s.n_basis * s.rate)
         bwd += T * (2 * 2.0 * 2 * M * s.n_basis * s.rate + 2.0 * s.n_basis * s.n_taps * s.rate)
     out = {"ms": ms, "templates": M, "seconds": T, "basis": [s.n_basis for s in half.slices], "loss": loss,
-           "flops": fwd + bwd, "tflops": (fwd + bwd) / (ms / 1e3) / 1e12}
+           "flops": fwd + bwd, "tflops": (fwd + bwd) / (ms / 1e3) / 1e12, "tiling": tiling}
     if refine_steps:
         from paper_2511_04730_amd.refine import refine
         smax2 = max(float(np.linalg.norm(s.mixing, 2)) ** 2 for s in half.slices)
@@ -646,7 +653,7 @@ def main() -> int:
 
     grad = None
     if args.grad_leg:
-        grad = grad_measure(refine_steps=args.refine_steps)
+        grad = grad_measure(refine_steps=args.refine_steps, tune=bool(args.autotune))
         log(f"gradient: {grad['ms']:.1f} ms per call ({grad['tflops']:.2f} TFLOP/s)")
 
     base = err = zs = None
